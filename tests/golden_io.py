@@ -1,0 +1,56 @@
+"""Readers for the hand-worked fixtures in tests/golden/ (no harmonic-sum arithmetic)."""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _kv(tokens):
+    out = {}
+    for t in tokens:
+        k, v = t.split("=", 1)
+        out[k] = v
+    return out
+
+
+def _ints(s):
+    return [int(v) for v in s.split(",") if v != ""]
+
+
+def read_1d(name="hand_1d.txt"):
+    spectra, cases = {}, []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "spectrum":
+                spectra[tok[1]] = np.array([float(v) for v in tok[2:]], dtype=np.float32)
+            elif tok[0] == "case":
+                kv = _kv(tok[3:])
+                mask = 0 if kv["mask"] == "all" else sum(1 << (k - 1) for k in _ints(kv["mask"]))
+                cases.append(dict(spectrum=tok[1], mode=tok[2], H=int(kv["H"]), mask=mask,
+                                  n=int(kv["n"]), S=_ints(kv["S"]), harm=int(kv["harm"]),
+                                  drift=int(kv["drift"])))
+    return spectra, cases
+
+
+def read_2d(name="hand_2d.txt"):
+    rows, cases = {}, []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "row":
+                rows[int(tok[1])] = [float(v) for v in tok[2:]]
+            elif tok[0] == "case":
+                kv = _kv(tok[2:])
+                cases.append(dict(mode=tok[1], H=int(kv["H"]), r=int(kv["r"]), z=int(kv["z"]),
+                                  S=_ints(kv["S"]), harm=int(kv["harm"]), drift=int(kv["drift"])))
+    zs = sorted(rows)
+    plane = np.array([rows[z] for z in zs], dtype=np.float32)
+    return plane, zs[0], zs[-1], cases

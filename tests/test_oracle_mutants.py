@@ -1,0 +1,81 @@
+"""Pin audit: plausible mistakes planted in the oracle must fail its pins.
+
+Each mutant is the oracle's C source with one plausible slip (a wrong sign or
+tie rule, a dropped term, a wrong index, a wrong truncation) or a Python-level
+slip in the normalisation, built into a temporary library and run against the
+pin tests in a child process.  A mutant that survives would mean the pins do
+not constrain that part of the oracle.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hs_oracle.c")
+PINS = ["tests/test_oracle_golden.py", "tests/test_oracle_stats.py", "tests/test_oracle_bruteforce.py",
+        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py"]
+
+C_MUTANTS = {
+    "greedy-tie-moves": ("if (b > a) { d += 1; v = b; }", "if (b >= a) { d += 1; v = b; }"),
+    "wrong-neighbour": ("k * n + d + 1);", "k * n + d + 2);"),
+    "dropped-term": ("S = S + v;", "S = v;"),
+    "snr-tie-to-larger-k": ("snr > best)", "snr >= best)"),
+    "no-mean": ("fmaf(S, rs[k - 1], nm[k - 1])", "fmaf(S, rs[k - 1], 0.0f)"),
+    "truncation-off-by-one": ("int64_t k = (len - 1) / reach;", "int64_t k = (len - 2) / reach;"),
+    "no-drift-in-sum": ("{ d += 1; v = b; } else { v = a; }", "{ d += 1; v = a; } else { v = a; }"),
+    "2d-row-not-scaled": ("int64_t row = k * z - z_min;", "int64_t row = z - z_min;"),
+    "drift-before-step": ("kb = (int32_t)k; db = (int32_t)d;", "kb = (int32_t)k; db = (int32_t)(d > 0 ? d - 1 : 0);"),
+}
+
+PY_MUTANTS = {
+    "sigma-scales-with-k": "import oracle, math\n"
+    "_t = oracle.tables\n"
+    "def tables(mu1, s1, H):\n"
+    "    mu, sig, rs, nm = _t(mu1, s1, H)\n"
+    "    import numpy as np\n"
+    "    k = np.arange(1, H + 1)\n"
+    "    return mu, sig * np.sqrt(k), (1.0 / (sig * np.sqrt(k))).astype(np.float32), (-(mu / (sig * np.sqrt(k)))).astype(np.float32)\n"
+    "oracle.tables = tables\n",
+    "variance-about-zero": "import oracle\n"
+    "_s = oracle.stats\n"
+    "def stats(x, first_bin=1):\n"
+    "    n, s1, s2 = oracle.exact_sums(x[..., first_bin:])\n"
+    "    return float(s1 / n), float(s2 / n)\n"
+    "oracle.stats = stats\n",
+}
+
+
+def _run_pins(env, prelude=""):
+    code = prelude + "import sys, pytest\nsys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider'] + %r))\n" % PINS
+    p = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env,
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, timeout=600)
+    return p.returncode
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTANTS))
+def test_c_mutant_is_caught(name, tmp_path):
+    old, new = C_MUTANTS[name]
+    src = open(SRC).read()
+    assert old in src, "mutation site vanished: " + name
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "mut.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-shared", "-fPIC", "-o", str(lib), str(mut), "-lm"],
+                   check=True)
+    env = dict(os.environ, HS_ORACLE_LIB=str(lib), PYTHONPATH=ROOT + os.pathsep + os.path.join(ROOT, "tests"))
+    assert _run_pins(env) != 0, "mutant survived: " + name
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_mutant_is_caught(name):
+    env = dict(os.environ, PYTHONPATH=ROOT + os.pathsep + os.path.join(ROOT, "tests"))
+    env.pop("HS_ORACLE_LIB", None)
+    assert _run_pins(env, PY_MUTANTS[name]) != 0, "mutant survived: " + name
+
+
+def test_unmutated_oracle_passes_pins():
+    env = dict(os.environ, PYTHONPATH=ROOT + os.pathsep + os.path.join(ROOT, "tests"))
+    env.pop("HS_ORACLE_LIB", None)
+    assert _run_pins(env) == 0
