@@ -1,0 +1,197 @@
+"""Benchmark of the harmonic-sum hot path on one MI355X.
+
+One step = one ``hs_sum_batched`` call over the batched workload (512
+DM-trial spectra of 2^20..2^22 FP32 bins, Exp(1) noise + 5 pulse trains each,
+H = 32, greedy, SNR > 6 candidate compaction): the per-spectrum FP64
+statistics, the float tables, the harmonic walk and the compaction.  Inputs
+are resident in HBM before the timed region.  Prints one JSON line.
+
+Also timed (extra keys): the plain per-spectrum FP32 path (one
+``hs_sum_1d`` per spectrum, dense outputs) and the FP16-storage batched path,
+plus the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+H = 32
+THRESHOLD = 6.0
+
+
+def keff_sum(lengths, H, greedy, first_bin=1):
+    """Sum over fundamentals of the harmonics summed (exact, per the truncation rule)."""
+    total = 0
+    for N in lengths:
+        N = int(N)
+        for k in range(1, H + 1):
+            # fundamentals n >= first_bin with k (n + greedy) <= N - 1
+            hi = (N - 1) // k - (1 if greedy else 0)
+            if hi >= first_bin:
+                total += min(hi, N - 1) - first_bin + 1
+    return total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--spectra", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the plain and FP16 legs")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="spectra in the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the harmonic-sum library runs on a single device "
+              "(independent spectra shard across GPUs by the caller); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic
+    from paper_2202_12817_amd import hs
+
+    dev = torch.device("cuda:0")
+    x, off = synthetic.config3(n_spectra=args.spectra, threads=16)
+    lengths = np.diff(off)
+    n_bins = int(x.size)
+    xt = torch.from_numpy(x).to(dev)
+    ot = torch.from_numpy(off).to(dev)
+    B = args.spectra
+    work = keff_sum(lengths, H, True)
+
+    plan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, max_spectra=B, threshold=THRESHOLD)
+    cap = 1 << 24
+    cand = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(p, xin):
+        hs.hs_sum_batched(p.handle, xin, ot, B, None, None, None, None, cand, cap, count, stream)
+
+    for _ in range(args.warmup):
+        step(plan, xt)
+    torch.cuda.synchronize()
+    hs.hs_plan_set_timing(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(plan, xt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    calls, norm_ms, sum_ms = hs.hs_plan_get_timing(plan.handle)
+    hs.hs_plan_set_timing(plan.handle, False)
+    n_cand = int(count.item())
+    ms_step = 1e3 * elapsed / args.steps
+    value = work * args.steps / elapsed
+
+    in_bytes = 4 * n_bins
+    cand_bytes = 16 * min(n_cand, cap)
+    sum_avg_ms = sum_ms / max(1, calls)
+    norm_avg_ms = norm_ms / max(1, calls)
+    achieved = (in_bytes + cand_bytes) / (sum_avg_ms * 1e-3) / 1e9
+
+    result = {
+        "metric": "spectral bins·harmonics/sec and achieved HBM GB/s (% of peak), plain vs batched/FP16",
+        "value": value,
+        "unit": "bin·harmonics/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched 1D greedy harmonic sum: %d spectra of 2^20..2^22 FP32 bins "
+                               "(Exp(1) noise + 5 pulse trains each), H=%d, SNR>%g candidate compaction"
+                               % (B, H, THRESHOLD),
+                   "spectra": B, "bins": n_bins, "H": H, "mode": "greedy", "threshold": THRESHOLD,
+                   "bin_harmonics": work, "candidates": n_cand},
+        "bins_per_s": n_bins * args.steps / elapsed,
+        "hbm_gbs_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9,
+        "hbm_frac_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "stage_ms": {"normalisation": norm_avg_ms, "harmonic_sum": sum_avg_ms},
+        "roofline": {"bound": "hbm", "kernel": "k_sum_1d<32,greedy,f32>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+
+    if not args.no_extra:
+        # plain: one hs_sum_1d per spectrum, dense outputs, no graph
+        pplan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, threshold=THRESHOLD)
+        nmax = int(lengths.max())
+        snr = torch.empty(nmax, dtype=torch.float32, device=dev)
+        harm = torch.empty(nmax, dtype=torch.uint8, device=dev)
+        drift = torch.empty(nmax, dtype=torch.uint8, device=dev)
+        base = xt.data_ptr()
+
+        def plain_step():
+            for s in range(B):
+                hs.hs_sum_1d(pplan.handle, base + 4 * int(off[s]), int(lengths[s]), None, snr, harm, drift, None,
+                             stream)
+        plain_step()
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_s = (time.perf_counter() - t0) / reps
+        pplan.close()
+        result["plain_fp32"] = {"value": work / plain_s, "ms_per_step": 1e3 * plain_s,
+                                "speedup_batched": plain_s / (ms_step * 1e-3)}
+        # FP16 storage with a per-spectrum scale
+        x16 = torch.empty(n_bins, dtype=torch.int16, device=dev)
+        for s in range(B):
+            scale = float(np.float32(x[off[s]:off[s + 1]].mean(dtype=np.float64)))
+            hs.hs_quantize_f16(base + 4 * int(off[s]), int(lengths[s]), scale, x16.data_ptr() + 2 * int(off[s]),
+                               stream)
+        plan16 = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F16, max_spectra=B, threshold=THRESHOLD)
+        for _ in range(args.warmup):
+            step(plan16, x16)
+        torch.cuda.synchronize()
+        hs.hs_plan_set_timing(plan16.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(plan16, x16)
+        torch.cuda.synchronize()
+        e16 = (time.perf_counter() - t0) / args.steps
+        c16, n16, s16 = hs.hs_plan_get_timing(plan16.handle)
+        n_cand16 = int(count.item())
+        plan16.close()
+        result["batched_fp16"] = {"value": work / e16, "ms_per_step": 1e3 * e16,
+                                  "speedup_vs_plain_fp32": plain_s / e16,
+                                  "hbm_gbs_compulsory": (2 * n_bins + 16 * n_cand16) / e16 / 1e9,
+                                  "stage_ms": {"normalisation": n16 / max(1, c16), "harmonic_sum": s16 / max(1, c16)},
+                                  "candidates": n_cand16}
+        del x16
+
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = list(range(min(args.cpu_sample, B)))
+        t0 = time.perf_counter()
+        for s in sample:
+            r = oracle.hs_1d(x[off[s]:off[s + 1]], H, oracle.GREEDY)
+            oracle.candidates(r["snr"], r["harm"], r["drift"], THRESHOLD, spectrum=s)
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": keff_sum(lengths[sample], H, True) / cpu_s, "unit": "bin·harmonics/s",
+                                  "cores": 1, "kind": "oracle",
+                                  "sample": "first %d spectra of the same batch (%d bins), float mirror, "
+                                            "exact statistics + per-fundamental C loops, one thread"
+                                            % (len(sample), int(lengths[sample].sum()))}
+    plan.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * hs.h -- incoherent harmonic sum on MI355X (gfx950): the C ABI.
+ *
+ * The operation (Adamek, Roy & Armour, "A Novel Greedy Approach To Harmonic
+ * Summing Using GPUs", arXiv:2202.12817):
+ *
+ *   For every fundamental bin n of a power spectrum x, form the partial sums
+ *   S_k of k harmonic elements, k = 1..H, normalise each to an SNR with the
+ *   mean and standard deviation of a k-element sum, and keep the best SNR,
+ *   its harmonic count and the drift of its last bin (Sec. 2, Eq. (1)-(2)).
+ *   Element k is
+ *     - simple sum (HS_STANDARD, Sec. 3.1, Eq. (3)):  x[k n];
+ *     - greedy sum (HS_GREEDY, Sec. 3.3, Eq. (5), Algorithm 2): the larger of
+ *       x[k n + d] and x[k n + d + 1]; when the second is strictly larger the
+ *       drift d grows by one.  Step k = 1 compares x[n] and x[n + 1].
+ *
+ * Conventions shared by every entry point:
+ *
+ *   - Normalisation (reading of Eq. (2) and GetMeanStdev of Algorithms 1-2):
+ *     mu1, var1 = population mean and variance of the stored powers of bins
+ *     [first_bin, N) (of the whole plane in 2D), each the exact value rounded
+ *     once to double; sigma1 = sqrt(var1) rounded once; mu_k = k mu1,
+ *     sigma_k = sqrt(k) sigma1.  The float SNR of a k-element sum is
+ *     fmaf(S_k, rs_k, nm_k) with rs_k = (float)(1/sigma_k) and
+ *     nm_k = (float)(-(mu_k/sigma_k)); S_k is summed in float in harmonic
+ *     order.  A caller may supply (mu1, sigma1) instead (`norm` arguments).
+ *     sigma1 zero or not finite: every output of that spectrum is zero.
+ *   - Truncation: harmonic k of fundamental n is summed only while every bin it
+ *     may read is inside the spectrum: k n <= N-1 (simple), k (n+1) <= N-1
+ *     (greedy).  Bins below first_bin or at/after fundamental_end are no
+ *     fundamental.  Every bin gets an output (zeros where no sum is formed).
+ *   - Best partial sum: the largest SNR among the k selected by harmonic_mask,
+ *     ties to the smaller k.  Outputs per bin: snr (float), harm = harmonic
+ *     count of the best sum (1..H, 0 = none), drift = the drift after that
+ *     harmonic (the last summed bin is harm * n + drift; 0 for HS_STANDARD).
+ *   - Memory: every array argument is DEVICE memory owned by the caller
+ *     (inputs, outputs, candidate buffers, counters), naturally aligned.  The
+ *     library owns only the plan and its internal workspace.  Inputs must stay
+ *     valid and outputs untouched until the stream has reached the end of the
+ *     call.  Powers must be finite.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Every
+ *     call only enqueues work; it does not synchronise.
+ *   - Errors: argument checks happen before anything is enqueued and return
+ *     HS_ERR_ARG / HS_ERR_UNSUPPORTED with nothing launched.  A failing HIP
+ *     call returns HS_ERR_HIP.  hs_last_error() returns a message for the
+ *     calling thread's last failure.  A plan must not be used from two host
+ *     threads at once; calls that overlap on the GPU through one plan race on
+ *     its workspace, so enqueue them on one stream.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hs_status {
+    HS_OK = 0,
+    HS_ERR_ARG = 1,          /* invalid argument (null pointer, size or range) */
+    HS_ERR_UNSUPPORTED = 2,  /* valid but not supported by this build (e.g. H > 32) */
+    HS_ERR_HIP = 3,          /* a HIP runtime call failed */
+    HS_ERR_NOMEM = 4         /* device allocation of the plan workspace failed */
+} hs_status;
+
+enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
+enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
+
+#define HS_MAX_HARMONICS 32
+
+/* Plan parameters.  Fill with hs_plan_desc_init, then override. */
+typedef struct hs_plan_desc {
+    int32_t  harmonics;        /* H, 1..HS_MAX_HARMONICS (default 32) */
+    int32_t  mode;             /* HS_STANDARD or HS_GREEDY (default HS_GREEDY) */
+    int32_t  dtype;            /* HS_F32 or HS_F16 (IEEE binary16 storage, decoded exactly) */
+    int32_t  first_bin;        /* >= 1; lowest fundamental and lowest bin in the statistics (default 1) */
+    uint64_t harmonic_mask;    /* bit k-1 set: the k-harmonic sum competes for the best; 0 = all (default) */
+    uint64_t report_mask;      /* hs_sum_1d only: bit k-1 set: export S_k (default 0) */
+    int64_t  fundamental_end;  /* fundamentals >= this give zeros; 0 = no limit (default) */
+    int32_t  max_spectra;      /* hs_sum_batched: most spectra per call (default 1024) */
+    float    threshold;        /* candidates: snr > threshold (default 6) */
+} hs_plan_desc;
+
+/* One candidate: a bin whose best SNR is strictly above the threshold. */
+typedef struct hs_candidate {
+    uint32_t spectrum;   /* index of the spectrum (0 for hs_sum_2d) */
+    uint32_t bin;        /* fundamental bin n (hs_sum_2d: row * n_r + column) */
+    float    snr;        /* best SNR */
+    uint16_t harm;       /* harmonic count of the best partial sum */
+    uint16_t drift;      /* drift after that harmonic */
+} hs_candidate;
+
+typedef struct hs_plan hs_plan;
+
+/* Fill *desc with the defaults listed above. */
+void hs_plan_desc_init(hs_plan_desc *desc);
+
+/*
+ * Validate *desc and create a plan on the current HIP device, allocating its
+ * workspace (statistics and tables for max_spectra spectra).  *plan is set on
+ * success and must be released with hs_plan_destroy.
+ */
+hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan);
+
+/* Release the plan (waits for nothing: the caller ensures no call is in flight). */
+hs_status hs_plan_destroy(hs_plan *plan);
+
+/*
+ * One spectrum (Eq. (3) or Algorithm 2 over all of its bins).
+ *   x        [n_bins] powers, dtype of the plan.  2 <= n_bins < 2^30.
+ *   norm     NULL: statistics from x; else [2] doubles (mu1, sigma1).
+ *   snr      [n_bins] float, harm [n_bins] uint8, drift [n_bins] uint8: dense
+ *            outputs indexed by fundamental bin; drift may be NULL.
+ *   partial  NULL, or [popcount(report_mask)][n_bins] floats: S_k for each
+ *            reported k in increasing k (0 where fewer than k harmonics fit).
+ */
+hs_status hs_sum_1d(hs_plan *plan, const void *x, int64_t n_bins, const double *norm,
+                    float *snr, uint8_t *harm, uint8_t *drift, float *partial, void *stream);
+
+/*
+ * A batch of independent spectra of any lengths, each with its own statistics,
+ * in one launch sequence (Sec. 4.3 processes 1024 spectra at once).
+ *   x          concatenated powers; spectrum s is x[offsets[s] .. offsets[s+1]).
+ *   offsets    [n_spectra + 1] int64, non-decreasing, offsets[0] = 0; each
+ *              spectrum 2 <= length < 2^30.  (Lengths are read on the device
+ *              and not re-validated there: keep them within these bounds.)
+ *   n_spectra  1..max_spectra of the plan (max_spectra <= 65535).
+ *   norm       NULL or [2 n_spectra] doubles (mu1, sigma1 per spectrum).
+ *   snr/harm/drift  NULL, or dense outputs indexed like x.
+ *   cand       NULL, or [cand_capacity] records of every bin with snr >
+ *              threshold, in unspecified order; *cand_count (device, zeroed
+ *              by the call) receives the true number of such bins even when
+ *              it exceeds cand_capacity (then only cand_capacity are written).
+ *   At least one of snr or cand must be given.
+ */
+hs_status hs_sum_batched(hs_plan *plan, const void *x, const int64_t *offsets, int32_t n_spectra,
+                         const double *norm, float *snr, uint8_t *harm, uint8_t *drift,
+                         hs_candidate *cand, int64_t cand_capacity,
+                         unsigned long long *cand_count, void *stream);
+
+/*
+ * The f-fdot form (Sec. 1 names it; reading: harmonic k of fundamental (r, z)
+ * is at column k r and row k z, and the sum stops before the first row outside
+ * [z_min, z_max]; greedy drift moves along r only; statistics over the plane).
+ *   plane      row i (z = z_min + i) starts at plane + i * row_stride; n_r
+ *              columns.  row_stride >= n_r.  2 <= n_r < 2^30.
+ *   z_min <= 0 <= z_max is not required; rows are z_min..z_max.
+ *   norm       NULL or [2] doubles.
+ *   snr/harm/drift  NULL, or dense [n_z][n_r] outputs (row stride n_r).
+ *   cand/cand_capacity/cand_count  as for hs_sum_batched (bin = i * n_r + r).
+ */
+hs_status hs_sum_2d(hs_plan *plan, const void *plane, int64_t n_r, int64_t row_stride,
+                    int32_t z_min, int32_t z_max, const double *norm,
+                    float *snr, uint8_t *harm, uint8_t *drift,
+                    hs_candidate *cand, int64_t cand_capacity,
+                    unsigned long long *cand_count, void *stream);
+
+/*
+ * Export the normalisation used by the most recent sum call on this plan
+ * (stream-ordered device-to-device copy of its first n entries).
+ *   mu_sigma  [2 n] doubles (mu1, sigma1); tables NULL or [n][2][H] floats
+ *             (rs_k for k = 1..H, then nm_k for k = 1..H); valid NULL or [n]
+ *             int32 (1 = usable normalisation, 0 = degenerate: zero outputs).
+ */
+hs_status hs_get_norm(hs_plan *plan, int32_t n, double *mu_sigma, float *tables,
+                      int32_t *valid, void *stream);
+
+/*
+ * FP16 storage of powers: out[i] = fp16_rne(clamp((float)x[i] / scale, +-65504))
+ * (one correctly rounded float division, then round-to-nearest-even to
+ * binary16).  scale > 0 and finite.  out is binary16 bit patterns.
+ */
+hs_status hs_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out, void *stream);
+
+/*
+ * Stage timing (profiling aid).  With timing enabled, every sum call records
+ * HIP events on its stream before and after its normalisation stage and after
+ * its harmonic-sum kernel.  hs_plan_get_timing waits for the recorded events,
+ * returns the number of timed calls and the summed milliseconds of the two
+ * stages (any pointer may be NULL), and clears the record.
+ */
+hs_status hs_plan_set_timing(hs_plan *plan, int32_t enable);
+hs_status hs_plan_get_timing(hs_plan *plan, int32_t *calls, double *norm_ms, double *sum_ms);
+
+const char *hs_status_string(hs_status status);
+const char *hs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HS_H */

@@ -1,0 +1,169 @@
+// Device-side helpers of the harmonic-sum library (gfx950): double-double
+// arithmetic for the normalisation statistics, buffer-resource loads for the
+// harmonic gathers, and the per-spectrum normalisation record.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hs.h"
+
+namespace hs {
+
+// Per-group (spectrum or plane) normalisation, written by the finalise kernel
+// and read (wave-uniformly) by the harmonic-sum kernels.
+struct NormRec {
+    double mu1;        // population mean of the stored powers, rounded once
+    double sigma1;     // sqrt of the population variance, rounded once
+    int32_t valid;     // 0: degenerate normalisation, all outputs zero
+    int32_t pad[3];
+    float2 t[HS_MAX_HARMONICS];   // (rs_k, nm_k) for k = 1..32
+};
+
+// Partial statistics of one chunk: exact-in-practice double-double sums.
+struct StatPart {
+    double s1hi, s1lo, s2hi, s2lo;
+};
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic (Knuth's TwoSum, Dekker's FastTwoSum, FMA-based
+// TwoProd).  Compiled with -ffp-contract=off so every operation is the single
+// IEEE rounding written here.
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void fast_two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    e = b - (s - a);
+}
+
+__device__ __forceinline__ dd dd_add_d(dd a, double b) {
+    double s, e;
+    two_sum(a.hi, b, s, e);
+    e = e + a.lo;
+    fast_two_sum(s, e, s, e);
+    return {s, e};
+}
+
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+    double s, e, t, f;
+    two_sum(a.hi, b.hi, s, e);
+    two_sum(a.lo, b.lo, t, f);
+    e = e + t;
+    fast_two_sum(s, e, s, e);
+    e = e + f;
+    fast_two_sum(s, e, s, e);
+    return {s, e};
+}
+
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+    double p = a.hi * b.hi;
+    double e = __builtin_fma(a.hi, b.hi, -p);
+    double c = a.hi * b.lo;
+    double c2 = a.lo * b.hi;
+    e = e + (c + c2);
+    double s;
+    fast_two_sum(p, e, s, e);
+    return {s, e};
+}
+
+// a / b for an exact double b (the element count).
+__device__ __forceinline__ dd dd_div_d(dd a, double b) {
+    double q1 = a.hi / b;
+    double p = q1 * b;
+    double pe = __builtin_fma(q1, b, -p);      // q1 * b = p + pe exactly
+    dd r = dd_add(a, dd{-p, -pe});
+    double q2 = r.hi / b;
+    double s, e;
+    fast_two_sum(q1, q2, s, e);
+    return {s, e};
+}
+
+// Correctly rounded double square root: the hardware-library result is
+// checked against both rounding midpoints with an exact residual and moved by
+// one ulp when it is on the wrong side.
+__device__ __forceinline__ double sqrt_rn(double v) {
+    if (!(v > 0.0) || !__builtin_isfinite(v)) return __builtin_sqrt(v);
+    double t = __builtin_sqrt(v);
+    for (int it = 0; it < 2; ++it) {
+        // neighbours of a positive finite double: adjacent bit patterns
+        double up = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, t) + 1u);
+        double dn = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, t) - 1u);
+        // midpoint m = (t + up) / 2 = t + h with h = (up - t) / 2 exact (power of two)
+        double h = (up - t) * 0.5;
+        // v - m^2 = (v - t^2) - 2 t h - h^2, each term exact in double-double
+        double p = t * t, pe = __builtin_fma(t, t, -p);
+        dd r = dd_add(dd{v, 0.0}, dd{-p, -pe});
+        r = dd_add_d(r, -(2.0 * t * h));
+        r = dd_add_d(r, -(h * h));
+        if (r.hi > 0.0 || (r.hi == 0.0 && r.lo > 0.0)) { t = up; continue; }
+        double hd = (t - dn) * 0.5;
+        dd q = dd_add(dd{v, 0.0}, dd{-p, -pe});
+        q = dd_add_d(q, 2.0 * t * hd);
+        q = dd_add_d(q, -(hd * hd));
+        if (q.hi < 0.0 || (q.hi == 0.0 && q.lo < 0.0)) { t = dn; continue; }
+        break;
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Buffer-resource loads: 32-bit byte offsets from a wave-uniform base; reads
+// outside num_records return zero instead of faulting.
+// ---------------------------------------------------------------------------
+constexpr int32_t kRsrcFlags = 0x00020000;   // gfx9 dword3: 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcFlags);
+}
+
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(elem * 4u), 0, 0));
+}
+
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 ld_f32x2(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    // bit-cast the whole 2-vector (a bit_cast of one element of the builtin's
+    // vector result would alias element 0)
+    const f32x2_t f = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(elem * 4u), 0, 0));
+    return make_float2(f.x, f.y);
+}
+
+__device__ __forceinline__ float ld_f16(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(elem * 2u), 0, 0);
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+
+__device__ __forceinline__ float2 ld_f16x2(__amdgpu_buffer_rsrc_t r, uint32_t elem) {
+    return make_float2(ld_f16(r, elem), ld_f16(r, elem + 1u));
+}
+
+template <bool F16>
+struct Loader;
+
+template <>
+struct Loader<false> {
+    static constexpr uint32_t kBytes = 4;
+    __device__ static float one(__amdgpu_buffer_rsrc_t r, uint32_t e) { return ld_f32(r, e); }
+    __device__ static float2 two(__amdgpu_buffer_rsrc_t r, uint32_t e) { return ld_f32x2(r, e); }
+};
+
+template <>
+struct Loader<true> {
+    static constexpr uint32_t kBytes = 2;
+    __device__ static float one(__amdgpu_buffer_rsrc_t r, uint32_t e) { return ld_f16(r, e); }
+    __device__ static float2 two(__amdgpu_buffer_rsrc_t r, uint32_t e) { return ld_f16x2(r, e); }
+};
+
+}  // namespace hs

@@ -1,0 +1,258 @@
+// Harmonic-sum kernels (gfx950).
+//
+// One lane owns one fundamental bin n and walks its harmonics k = 1..K in
+// order (the per-fundamental procedure of Sec. 3.1 Eq. (3) and Sec. 3.3
+// Eq. (5) / Algorithm 2):
+//   simple: v = x[k n]
+//   greedy: a = x[k n + d], b = x[k n + d + 1]; b > a ? (d++, v = b) : v = a
+//   S += v (float, harmonic order); snr = fma(S, rs_k, nm_k)  (Eq. (2))
+//   best: strictly larger SNR among the k selected by the mask.
+// Consecutive lanes own consecutive fundamentals, so harmonic k of a wave
+// reads a window of 64 k bins (strided by k); the greedy pair is one 8-byte
+// buffer load.  The normalisation table is wave-uniform and lives in SGPRs.
+// K = min(H, (N-1) / (n + greedy)) keeps every read inside the spectrum; the
+// buffer descriptors additionally bound every read by the spectrum's size.
+#include "hs_internal.h"
+
+namespace hs {
+namespace {
+
+// Result of one fundamental.
+struct Best {
+    float snr;
+    int harm;
+    int drift;
+};
+
+// Harmonic walk of fundamental n of one spectrum (descriptor r); K harmonics.
+// REPORT: also store S_k for the k in report_mask (slot-major, stride pstride).
+template <int HMAX, bool GREEDY, bool F16, bool REPORT>
+__device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K, const float2 *__restrict__ tab,
+                                     uint64_t kmask, uint64_t report_mask, float *partial, int64_t pstride) {
+    using L = Loader<F16>;
+    float S = 0.0f, best = 0.0f;
+    int kb = 0, db = 0;
+    uint32_t d = 0;
+    uint32_t m = n;   // k n
+#pragma unroll
+    for (int k = 1; k <= HMAX; ++k) {
+        if (k > K) break;
+        float v;
+        if constexpr (GREEDY) {
+            const float2 p = L::two(r, m + d);
+            const bool up = p.y > p.x;
+            v = up ? p.y : p.x;
+            d += up ? 1u : 0u;
+        } else {
+            v = L::one(r, m);
+        }
+        S = S + v;
+        const float2 t = tab[k - 1];
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        if constexpr (REPORT) {
+            if ((report_mask >> (k - 1)) & 1ull) {
+                const int slot = __builtin_popcountll(report_mask & ((1ull << (k - 1)) - 1ull));
+                partial[slot * pstride] = S;
+            }
+        }
+        if ((kmask >> (k - 1)) & 1ull) {
+            if (kb == 0 || snr > best) {
+                best = snr;
+                kb = k;
+                db = (int)d;
+            }
+        }
+        m += n;
+    }
+    return Best{kb ? best : 0.0f, kb, db};
+}
+
+// Candidate compaction of one wave: ballot, one atomic per wave, mbcnt rank.
+__device__ __forceinline__ void emit_candidate(bool pred, uint32_t spectrum, uint32_t bin, const Best &b,
+                                               hs_candidate *cand, int64_t cap, unsigned long long *count) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int lane = __lane_id();
+    const int leader = __builtin_ctzll(mask);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__builtin_popcountll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const unsigned long long slot = base + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        if ((int64_t)slot < cap) {
+            hs_candidate c;
+            c.spectrum = spectrum;
+            c.bin = bin;
+            c.snr = b.snr;
+            c.harm = (uint16_t)b.harm;
+            c.drift = (uint16_t)b.drift;
+            cand[slot] = c;
+        }
+    }
+}
+
+// 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock
+// fundamentals, tile t = blockIdx.x + j gridDim.x.
+template <int HMAX, bool GREEDY, bool F16>
+__global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
+    constexpr uint32_t eb = Loader<F16>::kBytes;
+    const int s = blockIdx.y;
+    int64_t off = 0, len = a.n_bins;
+    if (a.offsets) {
+        off = a.offsets[s];
+        len = a.offsets[s + 1] - off;
+        if (len < 0 || len >= (1ll << 30)) len = 0;   // malformed offsets: no output, no read
+    }
+    const NormRec *nr = a.norm + s;
+    const int valid = nr->valid;
+    const float2 *tab = nr->t;
+    const char *base = (const char *)a.x + off * eb;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(base, (uint32_t)(len * eb));
+    const int64_t n_end = a.n_end < len ? a.n_end : len;
+    for (int64_t t = blockIdx.x; t * kBlock < len; t += gridDim.x) {
+        const int64_t n = t * kBlock + threadIdx.x;
+        const bool in = n < len;
+        int K = 0;
+        if (in && valid && n >= a.first_bin && n < n_end) {
+            // 32-bit: len < 2^30
+            const uint32_t kk = (uint32_t)(len - 1) / (uint32_t)(GREEDY ? n + 1 : n);
+            K = kk < (uint32_t)a.H ? (int)kk : a.H;
+        }
+        Best b;
+        if (a.partial == nullptr) {
+            b = walk<HMAX, GREEDY, F16, false>(rsrc, (uint32_t)n, K, tab, a.kmask, 0, nullptr, 0);
+        } else {
+            float *prow = a.partial + off + n;
+            if (in)
+                for (uint64_t rm = a.report_mask, slot = 0; rm; rm &= rm - 1, ++slot) prow[slot * len] = 0.0f;
+            b = walk<HMAX, GREEDY, F16, true>(rsrc, (uint32_t)n, K, tab, a.kmask, a.report_mask, prow, len);
+        }
+        if (in) {
+            if (a.snr) a.snr[off + n] = b.snr;
+            if (a.harm) a.harm[off + n] = (uint8_t)b.harm;
+            if (a.drift) a.drift[off + n] = (uint8_t)b.drift;
+        }
+        if (a.cand) emit_candidate(in && b.harm > 0 && b.snr > a.thr, (uint32_t)s, (uint32_t)n, b, a.cand, a.cap,
+                                   a.count);
+    }
+}
+
+// f-fdot plane: blockIdx.y = row i (z = z_min + i), blockIdx.x = column tile.
+template <int HMAX, bool GREEDY, bool F16>
+__global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
+    using L = Loader<F16>;
+    constexpr uint32_t eb = L::kBytes;
+    const int i = blockIdx.y;
+    const int z = a.z_min + i;
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool in = r < a.n_r;
+    const NormRec *nr = a.norm;
+    const int valid = nr->valid;
+    const float2 *tab = nr->t;
+    int kz = a.H;
+    if (z > 0) kz = a.z_max / z;
+    if (z < 0) kz = a.z_min / z;
+    if (kz > a.H) kz = a.H;
+    int K = 0;
+    const int64_t n_end = a.n_end < a.n_r ? a.n_end : a.n_r;
+    if (in && valid && r >= a.first_bin && r < n_end) {
+        const uint32_t kk = (uint32_t)(a.n_r - 1) / (uint32_t)(GREEDY ? r + 1 : r);   // n_r < 2^30
+        K = kk < (uint32_t)kz ? (int)kk : kz;
+    }
+    const uint32_t row_bytes = (uint32_t)(a.n_r * eb);
+    float S = 0.0f, best = 0.0f;
+    int kb = 0, db = 0;
+    uint32_t d = 0, m = (uint32_t)r;
+#pragma unroll
+    for (int k = 1; k <= HMAX; ++k) {
+        if (k > K) break;
+        const int64_t row = (int64_t)k * z - a.z_min;    // inside [0, n_z) for k <= kz
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc((const char *)a.plane + row * a.stride * eb, row_bytes);
+        float v;
+        if constexpr (GREEDY) {
+            float2 p = L::two(rs, m + d);
+            bool up = p.y > p.x;
+            v = up ? p.y : p.x;
+            d += up ? 1u : 0u;
+        } else {
+            v = L::one(rs, m);
+        }
+        S = S + v;
+        const float2 t = tab[k - 1];
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        if ((a.kmask >> (k - 1)) & 1ull) {
+            if (kb == 0 || snr > best) {
+                best = snr;
+                kb = k;
+                db = (int)d;
+            }
+        }
+        m += (uint32_t)r;
+    }
+    const Best b{kb ? best : 0.0f, kb, db};
+    const int64_t o = (int64_t)i * a.n_r + r;
+    if (in) {
+        if (a.snr) a.snr[o] = b.snr;
+        if (a.harm) a.harm[o] = (uint8_t)b.harm;
+        if (a.drift) a.drift[o] = (uint8_t)b.drift;
+    }
+    if (a.cand) emit_candidate(in && b.harm > 0 && b.snr > a.thr, 0u, (uint32_t)o, b, a.cand, a.cap, a.count);
+}
+
+template <int HMAX>
+hipError_t sum1d_h(const SumArgs &a, bool greedy, bool f16, dim3 grid, hipStream_t st) {
+    if (greedy) {
+        if (f16)
+            hipLaunchKernelGGL((k_sum_1d<HMAX, true, true>), grid, dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sum_1d<HMAX, true, false>), grid, dim3(kBlock), 0, st, a);
+    } else {
+        if (f16)
+            hipLaunchKernelGGL((k_sum_1d<HMAX, false, true>), grid, dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sum_1d<HMAX, false, false>), grid, dim3(kBlock), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <int HMAX>
+hipError_t sum2d_h(const Sum2dArgs &a, bool greedy, bool f16, dim3 grid, hipStream_t st) {
+    if (greedy) {
+        if (f16)
+            hipLaunchKernelGGL((k_sum_2d<HMAX, true, true>), grid, dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sum_2d<HMAX, true, false>), grid, dim3(kBlock), 0, st, a);
+    } else {
+        if (f16)
+            hipLaunchKernelGGL((k_sum_2d<HMAX, false, true>), grid, dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sum_2d<HMAX, false, false>), grid, dim3(kBlock), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3 grid, hipStream_t st) {
+    switch (hmax) {
+        case 4: return sum1d_h<4>(a, greedy, f16, grid, st);
+        case 8: return sum1d_h<8>(a, greedy, f16, grid, st);
+        case 16: return sum1d_h<16>(a, greedy, f16, grid, st);
+        case 32: return sum1d_h<32>(a, greedy, f16, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, hipStream_t st) {
+    const int64_t n_z = (int64_t)a.z_max - a.z_min + 1;
+    dim3 grid((unsigned)((a.n_r + kBlock - 1) / kBlock), (unsigned)n_z);
+    switch (hmax) {
+        case 4: return sum2d_h<4>(a, greedy, f16, grid, st);
+        case 8: return sum2d_h<8>(a, greedy, f16, grid, st);
+        case 16: return sum2d_h<16>(a, greedy, f16, grid, st);
+        case 32: return sum2d_h<32>(a, greedy, f16, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hs

@@ -1,0 +1,200 @@
+"""ctypes binding of ``libhs.so`` (the C ABI of ``include/hs.h``).
+
+Argument marshalling only: every function here forwards to the C entry point
+of the same name.  Array arguments may be torch tensors (their device
+``data_ptr()`` is passed), plain integer device addresses, or ``None`` for a
+NULL pointer; ``stream`` may be a ``torch.cuda.Stream``, an integer
+``hipStream_t`` or ``None`` (torch's current stream).  A non-OK status raises
+:class:`HsError`.  The library must have been built (``build()`` of
+``__graft_entry__`` or ``python -m paper_2202_12817_amd.build``): there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhs.so")
+
+HS_OK, HS_ERR_ARG, HS_ERR_UNSUPPORTED, HS_ERR_HIP, HS_ERR_NOMEM = 0, 1, 2, 3, 4
+HS_STANDARD, HS_GREEDY = 0, 1
+HS_F32, HS_F16 = 0, 1
+HS_MAX_HARMONICS = 32
+
+EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched",
+            "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
+            "hs_status_string", "hs_last_error"]
+
+
+class HsPlanDesc(ctypes.Structure):
+    _fields_ = [("harmonics", ctypes.c_int32), ("mode", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("first_bin", ctypes.c_int32), ("harmonic_mask", ctypes.c_uint64),
+                ("report_mask", ctypes.c_uint64), ("fundamental_end", ctypes.c_int64),
+                ("max_spectra", ctypes.c_int32), ("threshold", ctypes.c_float)]
+
+
+class HsCandidate(ctypes.Structure):
+    _fields_ = [("spectrum", ctypes.c_uint32), ("bin", ctypes.c_uint32), ("snr", ctypes.c_float),
+                ("harm", ctypes.c_uint16), ("drift", ctypes.c_uint16)]
+
+
+CANDIDATE_BYTES = ctypes.sizeof(HsCandidate)
+
+
+class HsError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__("%s: %s (%s)" % (where, _status_string(status), message))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load ``libhs.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libhs.so is not built (%s); run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        lib.hs_plan_desc_init.argtypes = [ctypes.POINTER(HsPlanDesc)]
+        lib.hs_plan_desc_init.restype = None
+        lib.hs_plan_create.argtypes = [ctypes.POINTER(HsPlanDesc), ctypes.POINTER(vp)]
+        lib.hs_plan_destroy.argtypes = [vp]
+        lib.hs_sum_1d.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.hs_sum_batched.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        lib.hs_sum_2d.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        lib.hs_get_norm.argtypes = [vp, i32, vp, vp, vp, vp]
+        lib.hs_quantize_f16.argtypes = [vp, i64, ctypes.c_float, vp, vp]
+        lib.hs_plan_set_timing.argtypes = [vp, i32]
+        lib.hs_plan_get_timing.argtypes = [vp, vp, vp, vp]
+        lib.hs_status_string.argtypes = [ctypes.c_int]
+        lib.hs_status_string.restype = ctypes.c_char_p
+        lib.hs_last_error.argtypes = []
+        lib.hs_last_error.restype = ctypes.c_char_p
+        for name in ("hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d",
+                     "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _status_string(status):
+    try:
+        return load().hs_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - only used to format an error
+        return "status %d" % status
+
+
+def _check(status, where):
+    if status != HS_OK:
+        raise HsError(status, where, load().hs_last_error().decode())
+
+
+def _p(a):
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    return a.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def hs_plan_desc_init(**overrides) -> HsPlanDesc:
+    d = HsPlanDesc()
+    load().hs_plan_desc_init(ctypes.byref(d))
+    for k, v in overrides.items():
+        setattr(d, k, v)
+    return d
+
+
+def hs_plan_create(desc: HsPlanDesc) -> int:
+    h = ctypes.c_void_p()
+    _check(load().hs_plan_create(ctypes.byref(desc), ctypes.byref(h)), "hs_plan_create")
+    return h.value
+
+
+def hs_plan_destroy(plan: int) -> None:
+    _check(load().hs_plan_destroy(plan), "hs_plan_destroy")
+
+
+def hs_sum_1d(plan, x, n_bins, norm, snr, harm, drift, partial=None, stream=None):
+    _check(load().hs_sum_1d(plan, _p(x), int(n_bins), _p(norm), _p(snr), _p(harm), _p(drift), _p(partial),
+                            _stream(stream)), "hs_sum_1d")
+
+
+def hs_sum_batched(plan, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                   stream=None):
+    _check(load().hs_sum_batched(plan, _p(x), _p(offsets), int(n_spectra), _p(norm), _p(snr), _p(harm),
+                                 _p(drift), _p(cand), int(cand_capacity), _p(cand_count), _stream(stream)),
+           "hs_sum_batched")
+
+
+def hs_sum_2d(plan, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand=None, cand_capacity=0,
+              cand_count=None, stream=None):
+    _check(load().hs_sum_2d(plan, _p(plane), int(n_r), int(row_stride), int(z_min), int(z_max), _p(norm),
+                            _p(snr), _p(harm), _p(drift), _p(cand), int(cand_capacity), _p(cand_count),
+                            _stream(stream)), "hs_sum_2d")
+
+
+def hs_get_norm(plan, n, mu_sigma, tables=None, valid=None, stream=None):
+    _check(load().hs_get_norm(plan, int(n), _p(mu_sigma), _p(tables), _p(valid), _stream(stream)),
+           "hs_get_norm")
+
+
+def hs_quantize_f16(x, n, scale, out, stream=None):
+    _check(load().hs_quantize_f16(_p(x), int(n), float(scale), _p(out), _stream(stream)), "hs_quantize_f16")
+
+
+def hs_plan_set_timing(plan, enable: bool) -> None:
+    _check(load().hs_plan_set_timing(plan, 1 if enable else 0), "hs_plan_set_timing")
+
+
+def hs_plan_get_timing(plan):
+    """(calls, norm_ms, sum_ms) summed over the timed calls since the last read."""
+    c, a, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    _check(load().hs_plan_get_timing(plan, ctypes.byref(c), ctypes.byref(a), ctypes.byref(b)), "hs_plan_get_timing")
+    return c.value, a.value, b.value
+
+
+def hs_status_string(status: int) -> str:
+    return load().hs_status_string(status).decode()
+
+
+def hs_last_error() -> str:
+    return load().hs_last_error().decode()
+
+
+class Plan:
+    """Owns one ``hs_plan``; ``desc`` fields as keyword arguments."""
+
+    def __init__(self, **desc):
+        self.desc = hs_plan_desc_init(**desc)
+        self.handle = hs_plan_create(self.desc)
+
+    def close(self):
+        if self.handle:
+            hs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

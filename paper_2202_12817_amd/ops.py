@@ -1,0 +1,166 @@
+"""Torch-facing helpers around the C ABI: allocate outputs, pick the plan.
+
+Every result is computed by the HIP kernels of ``libhs.so``; these helpers
+only allocate device tensors and pass pointers.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import hs
+
+_MODES = {"standard": hs.HS_STANDARD, "greedy": hs.HS_GREEDY, hs.HS_STANDARD: hs.HS_STANDARD,
+          hs.HS_GREEDY: hs.HS_GREEDY}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return hs.HS_F32
+    if t.dtype in (torch.float16, torch.uint16, torch.int16):
+        return hs.HS_F16
+    raise TypeError("powers must be float32 or float16 (or their 16-bit patterns)")
+
+
+def _mask(ks) -> int:
+    m = 0
+    for k in ks:
+        m |= 1 << (int(k) - 1)
+    return m
+
+
+def make_plan(H, mode, dtype=hs.HS_F32, *, first_bin=1, harmonic_mask=0, report_mask=0, fundamental_end=0,
+              max_spectra=1, threshold=6.0) -> hs.Plan:
+    return hs.Plan(harmonics=int(H), mode=_MODES[mode], dtype=int(dtype), first_bin=int(first_bin),
+                   harmonic_mask=int(harmonic_mask), report_mask=int(report_mask),
+                   fundamental_end=int(fundamental_end), max_spectra=int(max_spectra),
+                   threshold=float(threshold))
+
+
+def _norm_tensor(norm, n, device):
+    if norm is None:
+        return None
+    t = torch.as_tensor(norm, dtype=torch.float64).reshape(-1)
+    if t.numel() != 2 * n:
+        raise ValueError("norm needs (mu1, sigma1) per spectrum")
+    return t.to(device)
+
+
+def sum_1d(x: torch.Tensor, H: int, mode="greedy", *, first_bin=1, harmonic_mask=0, fundamental_end=0,
+           report=(), norm=None, plan: hs.Plan | None = None, stream=None, with_norm=False):
+    """Dense harmonic sum of one spectrum; returns snr/harm/drift (+ partial, norm)."""
+    n = x.numel()
+    own = plan is None
+    if own:
+        plan = make_plan(H, mode, _dtype_code(x), first_bin=first_bin, harmonic_mask=harmonic_mask,
+                         report_mask=_mask(report), fundamental_end=fundamental_end)
+    dev = x.device
+    snr = torch.empty(n, dtype=torch.float32, device=dev)
+    harm = torch.empty(n, dtype=torch.uint8, device=dev)
+    drift = torch.empty(n, dtype=torch.uint8, device=dev)
+    partial = torch.empty((len(report), n), dtype=torch.float32, device=dev) if len(report) else None
+    nt = _norm_tensor(norm, 1, dev)
+    hs.hs_sum_1d(plan.handle, x, n, nt, snr, harm, drift, partial, stream)
+    out = dict(snr=snr, harm=harm, drift=drift, partial=partial)
+    if with_norm:
+        out.update(get_norm(plan, 1, plan.desc.harmonics, dev, stream))
+    if own:
+        torch.cuda.synchronize(dev)
+        plan.close()
+    return out
+
+
+def get_norm(plan: hs.Plan, n: int, H: int, device, stream=None):
+    """(mu1, sigma1), float tables [n, 2, H] and validity of the last call's spectra."""
+    ms = torch.empty(2 * n, dtype=torch.float64, device=device)
+    tab = torch.empty((n, 2, H), dtype=torch.float32, device=device)
+    valid = torch.empty(n, dtype=torch.int32, device=device)
+    hs.hs_get_norm(plan.handle, n, ms, tab, valid, stream)
+    return dict(mu_sigma=ms.view(n, 2), tables=tab, valid=valid)
+
+
+def sum_batched(x: torch.Tensor, offsets: torch.Tensor, H: int, mode="greedy", threshold=6.0, *, first_bin=1,
+                harmonic_mask=0, fundamental_end=0, dense=False, candidates=True, capacity=None, norm=None,
+                plan: hs.Plan | None = None, stream=None, with_norm=False):
+    """Batch of spectra ``x[offsets[s]:offsets[s+1]]``; candidates and/or dense outputs."""
+    B = offsets.numel() - 1
+    dev = x.device
+    own = plan is None
+    if own:
+        plan = make_plan(H, mode, _dtype_code(x), first_bin=first_bin, harmonic_mask=harmonic_mask,
+                         fundamental_end=fundamental_end, max_spectra=B, threshold=threshold)
+    out = {}
+    snr = harm = drift = cand = count = None
+    if dense:
+        snr = torch.empty(x.numel(), dtype=torch.float32, device=dev)
+        harm = torch.empty(x.numel(), dtype=torch.uint8, device=dev)
+        drift = torch.empty(x.numel(), dtype=torch.uint8, device=dev)
+        out.update(snr=snr, harm=harm, drift=drift)
+    cap = 0
+    if candidates:
+        cap = int(capacity) if capacity is not None else max(1024, x.numel() // 64)
+        cand = torch.empty((cap, hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        out.update(cand_raw=cand, count=count)
+    nt = _norm_tensor(norm, B, dev)
+    hs.hs_sum_batched(plan.handle, x, offsets, B, nt, snr, harm, drift, cand, cap, count, stream)
+    if with_norm:
+        out.update(get_norm(plan, B, plan.desc.harmonics, dev, stream))
+    if own:
+        torch.cuda.synchronize(dev)
+        plan.close()
+    return out
+
+
+def sum_2d(plane: torch.Tensor, z_min: int, z_max: int, H: int, mode="greedy", *, first_bin=1, harmonic_mask=0,
+           fundamental_end=0, dense=True, candidates=False, threshold=6.0, capacity=None, norm=None,
+           plan: hs.Plan | None = None, stream=None, with_norm=False):
+    """f-fdot plane [n_z, n_r] (row stride from the tensor); dense planes and/or candidates."""
+    n_z, n_r = plane.shape
+    if n_z != z_max - z_min + 1:
+        raise ValueError("plane rows do not match z range")
+    if plane.stride(1) != 1:
+        raise ValueError("plane columns must be contiguous")
+    dev = plane.device
+    own = plan is None
+    if own:
+        plan = make_plan(H, mode, _dtype_code(plane), first_bin=first_bin, harmonic_mask=harmonic_mask,
+                         fundamental_end=fundamental_end, threshold=threshold)
+    out = {}
+    snr = harm = drift = cand = count = None
+    if dense:
+        snr = torch.empty((n_z, n_r), dtype=torch.float32, device=dev)
+        harm = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
+        drift = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
+        out.update(snr=snr, harm=harm, drift=drift)
+    cap = 0
+    if candidates:
+        cap = int(capacity) if capacity is not None else max(1024, plane.numel() // 64)
+        cand = torch.empty((cap, hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        out.update(cand_raw=cand, count=count)
+    nt = _norm_tensor(norm, 1, dev)
+    hs.hs_sum_2d(plan.handle, plane, n_r, plane.stride(0), z_min, z_max, nt, snr, harm, drift, cand, cap, count,
+                 stream)
+    if with_norm:
+        out.update(get_norm(plan, 1, plan.desc.harmonics, dev, stream))
+    if own:
+        torch.cuda.synchronize(dev)
+        plan.close()
+    return out
+
+
+def quantize_f16(x: torch.Tensor, scale: float, stream=None) -> torch.Tensor:
+    """FP16 storage of float32 powers (binary16 patterns viewed as float16)."""
+    out = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+    hs.hs_quantize_f16(x, x.numel(), scale, out, stream)
+    return out.view(torch.float16)
+
+
+def candidates_numpy(out, limit=None):
+    """Copy candidate records to a numpy structured array (host)."""
+    import numpy as np
+    dt = np.dtype([("spectrum", "<u4"), ("bin", "<u4"), ("snr", "<f4"), ("harm", "<u2"), ("drift", "<u2")])
+    n = int(out["count"].item())
+    m = min(n, out["cand_raw"].shape[0]) if limit is None else min(n, limit)
+    raw = out["cand_raw"][:m].cpu().numpy()
+    return raw.view(dt).reshape(-1), n

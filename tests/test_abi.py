@@ -1,0 +1,122 @@
+"""The C-ABI library loads and exports every entry point of include/hs.h.
+
+No compute call is made here (no GPU in this environment): only symbol
+presence and the argument checks that return before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2202_12817_amd import hs
+    return hs.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hs_plan_create", "hs_sum_1d", "hs_sum_2d", "hs_sum_batched"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2202_12817_amd import hs
+    names = declared_functions()
+    assert set(names) == set(hs.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    from paper_2202_12817_amd import hs
+    assert ctypes.sizeof(hs.HsCandidate) == 16
+    assert ctypes.sizeof(hs.HsPlanDesc) == 48
+
+
+def test_desc_defaults(lib):
+    from paper_2202_12817_amd import hs
+    d = hs.hs_plan_desc_init()
+    assert (d.harmonics, d.mode, d.dtype, d.first_bin) == (32, hs.HS_GREEDY, hs.HS_F32, 1)
+    assert d.harmonic_mask == 0 and d.report_mask == 0 and d.fundamental_end == 0
+    assert d.max_spectra == 1024 and d.threshold == pytest.approx(6.0)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("harmonics", 0, 1), ("harmonics", 33, 2), ("mode", 7, 1), ("dtype", 5, 1), ("first_bin", 0, 1),
+    ("max_spectra", 0, 1), ("max_spectra", 70000, 1), ("fundamental_end", -1, 1),
+])
+def test_plan_create_rejects_bad_desc(lib, field, value, status):
+    from paper_2202_12817_amd import hs
+    d = hs.hs_plan_desc_init(**{field: value})
+    h = ctypes.c_void_p()
+    assert lib.hs_plan_create(ctypes.byref(d), ctypes.byref(h)) == status
+    assert h.value is None
+    assert lib.hs_last_error()
+
+
+def test_masks_must_fit_h(lib):
+    from paper_2202_12817_amd import hs
+    h = ctypes.c_void_p()
+    d = hs.hs_plan_desc_init(harmonics=4, report_mask=1 << 5)
+    assert lib.hs_plan_create(ctypes.byref(d), ctypes.byref(h)) == hs.HS_ERR_ARG
+    d = hs.hs_plan_desc_init(harmonics=4, harmonic_mask=1 << 10)
+    assert lib.hs_plan_create(ctypes.byref(d), ctypes.byref(h)) == hs.HS_ERR_ARG
+
+
+def test_null_plan_and_pointers_rejected(lib):
+    from paper_2202_12817_amd import hs
+    assert lib.hs_sum_1d(None, 16, 100, None, 16, 16, None, None, None) == hs.HS_ERR_ARG
+    assert lib.hs_sum_batched(None, 16, 16, 1, None, 16, 16, None, None, 0, None, None) == hs.HS_ERR_ARG
+    assert lib.hs_sum_2d(None, 16, 10, 10, 0, 0, None, 16, 16, None, None, 0, None, None) == hs.HS_ERR_ARG
+    assert lib.hs_get_norm(None, 1, 16, None, None, None) == hs.HS_ERR_ARG
+    assert lib.hs_plan_destroy(None) == hs.HS_ERR_ARG
+    assert lib.hs_plan_create(None, None) == hs.HS_ERR_ARG
+
+
+def test_quantize_argument_checks(lib):
+    from paper_2202_12817_amd import hs
+    assert lib.hs_quantize_f16(16, 10, ctypes.c_float(0.0), 16, None) == hs.HS_ERR_ARG
+    assert lib.hs_quantize_f16(16, 10, ctypes.c_float(float("inf")), 16, None) == hs.HS_ERR_ARG
+    assert lib.hs_quantize_f16(None, 10, ctypes.c_float(1.0), 16, None) == hs.HS_ERR_ARG
+    assert lib.hs_quantize_f16(16, -1, ctypes.c_float(1.0), 16, None) == hs.HS_ERR_ARG
+    assert lib.hs_quantize_f16(16, 0, ctypes.c_float(1.0), 16, None) == hs.HS_OK
+
+
+def test_status_strings(lib):
+    from paper_2202_12817_amd import hs
+    for s in range(5):
+        assert hs.hs_status_string(s)
+    assert hs.hs_status_string(99) == "unknown status"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2202_12817_amd import hs
+    saved = hs._lib
+    try:
+        hs._lib = None
+        with pytest.raises(RuntimeError, match="not built"):
+            hs.load(str(tmp_path / "absent.so"))
+    finally:
+        hs._lib = saved
+
+
+def test_product_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_2202_12817_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "hs_oracle" not in text, f
