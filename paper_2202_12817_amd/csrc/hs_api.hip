@@ -30,7 +30,8 @@ int bucket(int H) {
     return 32;
 }
 
-bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+// natural alignment of the stored powers
+bool aligned_elem(const void *p, int dtype) { return ((uintptr_t)p & (dtype == HS_F16 ? 1u : 3u)) == 0; }
 
 uint64_t eligible_mask(const hs_plan_desc &d) {
     const uint64_t all = d.harmonics >= 64 ? ~0ull : ((1ull << d.harmonics) - 1ull);
@@ -153,7 +154,7 @@ hs_status hs_sum_1d(hs_plan *p, const void *x, int64_t n_bins, const double *nor
                     uint8_t *drift, float *partial, void *stream) {
     if (!p || !x || !snr || !harm) return fail(HS_ERR_ARG, "null argument");
     if (n_bins < 2 || n_bins >= (1ll << 30)) return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30)");
-    if (!aligned16(x)) return fail(HS_ERR_ARG, "x must be 16-byte aligned");
+    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
     if (p->desc.report_mask != 0 && !partial) return fail(HS_ERR_ARG, "report_mask set but partial is NULL");
     hipStream_t st = (hipStream_t)stream;
     hs::StatsArgs sa{};
@@ -195,7 +196,7 @@ hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int3
                          unsigned long long *cand_count, void *stream) {
     if (!p || !x || !offsets) return fail(HS_ERR_ARG, "null argument");
     if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
-    if (!aligned16(x)) return fail(HS_ERR_ARG, "x must be 16-byte aligned");
+    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
     if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
     if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
     if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
@@ -247,7 +248,7 @@ hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stri
     if (z_max < z_min) return fail(HS_ERR_ARG, "z_max < z_min");
     const int64_t n_z = (int64_t)z_max - z_min + 1;
     if (n_z > 65535) return fail(HS_ERR_UNSUPPORTED, "more than 65535 rows");
-    if (!aligned16(plane)) return fail(HS_ERR_ARG, "plane must be 16-byte aligned");
+    if (!aligned_elem(plane, p->desc.dtype)) return fail(HS_ERR_ARG, "plane must be aligned to its element size");
     if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
     if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
     if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");

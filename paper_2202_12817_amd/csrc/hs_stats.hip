@@ -56,10 +56,10 @@ __device__ __forceinline__ void acc1(dd &s1, dd &s2, float v) {
     s2 = dd_add_d(s2, dv * dv);      // the square of a float is exact in double
 }
 
-// Accumulate elements [lo, hi) of the array x (element units).  The full
-// 16-byte vectors inside the range are read with aligned vector loads (x
-// itself is 16-byte aligned); the ragged head and tail element by element,
-// so nothing outside [lo, hi) is read.
+// Accumulate elements [lo, hi) of the array x (element units; x 16-byte
+// aligned).  The full 16-byte vectors inside the range are read with vector
+// loads, the ragged head and tail element by element, so nothing outside
+// [lo, hi) is read.
 template <bool F16>
 __device__ __forceinline__ void accumulate(const char *x, int64_t lo, int64_t hi, dd &s1, dd &s2) {
     constexpr int64_t V = F16 ? 8 : 4;
@@ -96,9 +96,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(StatsArgs a) {
     const int64_t W = G.row_len > f0 ? G.row_len - f0 : 0;   // counted bins per row
     const int64_t V = W * G.rows;                               // counted bins per group
     const int64_t v_lo = V * c / a.chunks, v_hi = V * (c + 1) / a.chunks;
-    // element offset of the group start from the 16-byte aligned array start
+    // element offsets are taken from the 16-byte aligned address at or below
+    // the array start, so vector loads are aligned whatever x's alignment
     constexpr int64_t eb = F16 ? 2 : 4;
-    const int64_t gofs = (G.base - (const char *)a.x) / eb;
+    const int64_t mis = (int64_t)(((uintptr_t)a.x & 15u) / eb);
+    const char *xa = (const char *)a.x - mis * eb;
+    const int64_t gofs = (G.base - (const char *)a.x) / eb + mis;
     dd s1{0.0, 0.0}, s2{0.0, 0.0};
     int64_t v = v_lo;
     while (v < v_hi) {                       // walk the rows the chunk covers
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(StatsArgs a) {
         int64_t n = W - (col - f0);
         if (n > v_hi - v) n = v_hi - v;
         int64_t e0 = gofs + r * G.stride + col;
-        accumulate<F16>((const char *)a.x, e0, e0 + n, s1, s2);
+        accumulate<F16>(xa, e0, e0 + n, s1, s2);
         v += n;
     }
     __shared__ dd sh1[kBlock], sh2[kBlock];

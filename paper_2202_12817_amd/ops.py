@@ -98,7 +98,7 @@ def sum_batched(x: torch.Tensor, offsets: torch.Tensor, H: int, mode="greedy", t
     cap = 0
     if candidates:
         cap = int(capacity) if capacity is not None else max(1024, x.numel() // 64)
-        cand = torch.empty((cap, hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
+        cand = torch.empty((max(cap, 1), hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
         count = torch.zeros(1, dtype=torch.int64, device=dev)
         out.update(cand_raw=cand, count=count)
     nt = _norm_tensor(norm, B, dev)
@@ -135,7 +135,7 @@ def sum_2d(plane: torch.Tensor, z_min: int, z_max: int, H: int, mode="greedy", *
     cap = 0
     if candidates:
         cap = int(capacity) if capacity is not None else max(1024, plane.numel() // 64)
-        cand = torch.empty((cap, hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
+        cand = torch.empty((max(cap, 1), hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
         count = torch.zeros(1, dtype=torch.int64, device=dev)
         out.update(cand_raw=cand, count=count)
     nt = _norm_tensor(norm, 1, dev)

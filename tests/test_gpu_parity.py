@@ -136,6 +136,16 @@ def test_1d_caller_normalisation(dev, mode):
         check_dense(got, oracle.hs_1d(x, 16, MODES[mode], norm=norm), None, "norm %r" % (norm,))
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_1d_unaligned_start(dev, shift):
+    x = synthetic.exp_noise(100003, 43)
+    buf = torch.zeros(x.size + 8, dtype=torch.float32, device=dev)
+    buf[shift:shift + x.size] = torch.from_numpy(x).to(dev)
+    got = _ops().sum_1d(buf[shift:shift + x.size], 32, "greedy", with_norm=True)
+    check_dense(got, oracle.hs_1d(x, 32, oracle.GREEDY), None, "shift %d" % shift)
+    check_norm(got, x, 1, 32, "shift %d" % shift)
+
+
 def test_1d_degenerate_spectrum_gives_zeros(dev):
     x = np.full(5000, 2.5, dtype=np.float32)
     for mode in ("standard", "greedy"):
@@ -218,7 +228,8 @@ def test_batched_small(dev, mode, f16):
         xt = torch.from_numpy(x).to(dev)
     ot = torch.from_numpy(off).to(dev)
     print("batched", mode, f16, flush=True)
-    got = _ops().sum_batched(xt, ot, 32, mode, thr, dense=True, candidates=True, with_norm=True)
+    got = _ops().sum_batched(xt, ot, 32, mode, thr, dense=True, candidates=True, capacity=x.size,
+                             with_norm=True)
     w = oracle.hs_batched(x, off, 32, MODES[mode], thr, dense=True)
     ms = _np(got["mu_sigma"])
     for s in range(B):
@@ -315,7 +326,7 @@ def test_2d_strided_rows_and_candidates(dev):
     full = _plane(z_max - z_min + 1, stride, 9)
     pt = torch.from_numpy(full).to(dev)[:, :n_r]
     p = full[:, :n_r].copy()
-    got = _ops().sum_2d(pt, z_min, z_max, 16, "greedy", candidates=True, threshold=3.0)
+    got = _ops().sum_2d(pt, z_min, z_max, 16, "greedy", candidates=True, threshold=3.0, capacity=p.size)
     w = oracle.hs_2d(p, z_min, z_max, 16, oracle.GREEDY)
     check_dense(got, w, None, "strided")
     recs, n = _cands(got)
