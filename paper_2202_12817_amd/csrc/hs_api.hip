@@ -2,6 +2,7 @@
 // management and the launch sequence of every entry point (declared and
 // documented in include/hs.h).
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -78,6 +79,36 @@ hs_status run_norm(hs_plan *p, hs::StatsArgs sa, int groups, hipStream_t st) {
     return mark(p, 1, st);
 }
 
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+// Shape of the persistent batched launch: one work queue per XCD, as many
+// workgroups as are resident.  HS_XCD_F and HS_XCD_WGS_PER_CU override the
+// defaults (tuning aids).
+hs_status setup_xcd(hs_plan *p) {
+    hipError_t e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute(CUs)");
+    int nx = 0;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess || nx < 1) {
+        (void)hipGetLastError();
+        nx = 1;
+    }
+    if (nx > hs::kMaxXcd) nx = hs::kMaxXcd;
+    p->n_xcd = nx;
+    int F = env_int("HS_XCD_F", 4);
+    p->xcd_f = (F == 1 || F == 2 || F == 4) ? F : 4;
+    int per_cu = 0;
+    e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f, &per_cu);
+    if (e != hipSuccess) return fail_hip(e, "occupancy query");
+    int want = env_int("HS_XCD_WGS_PER_CU", 4);
+    if (want >= 1 && want < per_cu) per_cu = want;
+    if (per_cu < 1) per_cu = 1;
+    p->xcd_blocks = per_cu * p->n_cu;
+    return HS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -127,11 +158,18 @@ hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
     }
     e = hipMalloc((void **)&p->norm, sizeof(hs::NormRec) * (size_t)p->max_groups);
     if (e == hipSuccess) e = hipMalloc((void **)&p->parts, sizeof(hs::StatPart) * (size_t)p->parts_cap);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->tickets, sizeof(uint32_t) * hs::kMaxXcd);
     if (e != hipSuccess) {
         if (p->norm) (void)hipFree(p->norm);
+        if (p->parts) (void)hipFree(p->parts);
         delete p;
         (void)hipGetLastError();
         return fail(HS_ERR_NOMEM, "device workspace allocation failed");
+    }
+    hs_status ss = setup_xcd(p);
+    if (ss != HS_OK) {
+        hs_plan_destroy(p);
+        return ss;
     }
     *plan = p;
     return HS_OK;
@@ -144,6 +182,7 @@ hs_status hs_plan_destroy(hs_plan *p) {
     (void)hipSetDevice(p->device);
     (void)hipFree(p->norm);
     (void)hipFree(p->parts);
+    (void)hipFree(p->tickets);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
     delete p;
@@ -233,8 +272,15 @@ hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int3
     a.cap = cand_capacity;
     a.count = cand_count;
     a.thr = p->desc.threshold;
-    dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
-    e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
+    hs::XcdArgs xa{};
+    xa.s = a;
+    xa.n_spectra = n_spectra;
+    xa.n_xcd = p->n_xcd;
+    xa.tickets = p->tickets;
+    e = hs::launch_zero_u32(p->tickets, p->n_xcd, st);
+    if (e != hipSuccess) return fail_hip(e, "ticket reset");
+    e = hs::launch_sum_xcd(xa, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f,
+                           p->xcd_blocks, st);
     if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
     return mark(p, 2, st);
 }

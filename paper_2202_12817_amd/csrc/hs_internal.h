@@ -14,7 +14,8 @@ constexpr int kBlock = 256;          // threads per harmonic-sum / statistics bl
 constexpr int kChunksBatched = 64;   // statistics chunks per spectrum of a batch
 constexpr int kChunks1D = 512;       // statistics chunks of a single spectrum
 constexpr int kChunks2D = 2048;      // statistics chunks of a plane
-constexpr int kTileBlocksBatched = 96;   // harmonic-sum blocks per spectrum of a batch
+constexpr int kTileBlocksBatched = 96;   // plain kernel: blocks per spectrum of a batch
+constexpr int kMaxXcd = 64;              // work-queue counters in the plan workspace
 
 // Where the statistics of group g (spectrum or plane) come from: `rows` rows
 // of `row_len` powers, row r starting at element base(g) + r * stride, bins
@@ -74,11 +75,22 @@ struct Sum2dArgs {
     float thr;
 };
 
+// Persistent XCD-aware batched harmonic sum (see hs_sum_xcd.hip).
+struct XcdArgs {
+    SumArgs s;
+    int32_t n_spectra;
+    int32_t n_xcd;            // virtual XCDs (work queues), >= 1
+    uint32_t *tickets;        // [n_xcd] chunk counters, zero at launch
+};
+
 hipError_t launch_stats(const StatsArgs &a, int groups, bool f16, hipStream_t st);
 hipError_t launch_finalize(const StatsArgs &a, int groups, hipStream_t st);
 hipError_t launch_export_norm(const NormRec *norm, int n, int H, double *mu_sigma, float *tables,
                               int32_t *valid, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
+hipError_t xcd_resident_blocks(int hmax, bool greedy, bool f16, int F, int *per_cu);
+hipError_t launch_sum_xcd(const XcdArgs &a, int hmax, bool greedy, bool f16, int F, int blocks, hipStream_t st);
 hipError_t launch_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out, hipStream_t st);
 hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3 grid, hipStream_t st);
 hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, hipStream_t st);
@@ -96,6 +108,10 @@ struct hs_plan {
     hs::NormRec *norm;           // device [max_groups]
     hs::StatPart *parts;         // device [parts_cap]
     int last_groups;             // groups written by the most recent call
+    uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the batched kernel
+    int n_cu, n_xcd;             // device shape
+    int xcd_f;                   // fundamentals per lane of the batched kernel
+    int xcd_blocks;              // persistent grid of the batched kernel
     bool timing;                 // record stage events on every call
     std::vector<hipEvent_t> ev;  // 3 events per timed call: start, after norm, after sum
     int ev_used;                 // events of timed calls not yet read

@@ -231,6 +231,10 @@ __global__ void k_zero_u64(unsigned long long *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
 
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
 __global__ __launch_bounds__(kBlock) void k_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         float y = x[i] / scale;                        // correctly rounded float division
@@ -264,6 +268,11 @@ hipError_t launch_export_norm(const NormRec *norm, int n, int H, double *mu_sigm
 
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p, n);
     return hipGetLastError();
 }
 
