@@ -67,6 +67,12 @@ typedef enum hs_status {
 
 enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
 enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
+/* hs_plan_desc.kernel: which 1D kernel runs.  AUTO = PERSISTENT except when
+ * partial sums are reported (hs_sum_1d with report_mask), which uses PLAIN.
+ * PLAIN is the design the paper describes for its GPU sum (Sec. 3.1.1): one
+ * thread per fundamental bin, a grid per spectrum.  PERSISTENT is the
+ * XCD-aware work-queue kernel (same results, bit for bit). */
+enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
 
 #define HS_MAX_HARMONICS 32
 
@@ -81,6 +87,7 @@ typedef struct hs_plan_desc {
     int64_t  fundamental_end;  /* fundamentals >= this give zeros; 0 = no limit (default) */
     int32_t  max_spectra;      /* hs_sum_batched: most spectra per call (default 1024) */
     float    threshold;        /* candidates: snr > threshold (default 6) */
+    int32_t  kernel;           /* HS_KERNEL_AUTO (default), HS_KERNEL_PERSISTENT or HS_KERNEL_PLAIN */
 } hs_plan_desc;
 
 /* One candidate: a bin whose best SNR is strictly above the threshold. */

@@ -61,6 +61,23 @@ hs_status mark(hs_plan *p, int stage, hipStream_t st) {
     return HS_OK;
 }
 
+// The persistent kernel over n spectra (offsets == NULL: one spectrum of
+// a.n_bins).
+hs_status run_persistent(hs_plan *p, const hs::SumArgs &a, int n, hipStream_t st) {
+    hs::XcdArgs xa{};
+    xa.s = a;
+    xa.n_spectra = n;
+    xa.n_xcd = p->n_xcd;
+    xa.tickets = p->tickets;
+    xa.prefix = p->prefix;
+    hipError_t e = hs::launch_zero_u32(p->tickets, p->n_xcd, st);
+    if (e != hipSuccess) return fail_hip(e, "ticket reset");
+    e = hs::launch_sum_xcd(xa, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f,
+                           p->xcd_blocks, st);
+    if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    return HS_OK;
+}
+
 // Statistics and tables of `groups` groups (or the caller's normalisation).
 hs_status run_norm(hs_plan *p, hs::StatsArgs sa, int groups, hipStream_t st) {
     hipError_t e;
@@ -98,11 +115,13 @@ hs_status setup_xcd(hs_plan *p) {
     if (nx > hs::kMaxXcd) nx = hs::kMaxXcd;
     p->n_xcd = nx;
     int F = env_int("HS_XCD_F", 4);
-    p->xcd_f = (F == 1 || F == 2 || F == 4) ? F : 4;
+    p->xcd_f = (F == 2 || F == 4) ? F : 4;
     int per_cu = 0;
     e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f, &per_cu);
     if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    int want = env_int("HS_XCD_WGS_PER_CU", 4);
+    // measured on MI355X (512 spectra, H = 32): FP32 is fastest at 4 resident
+    // workgroups per CU (more in flight thrashes the XCD's L2), FP16 at full occupancy
+    int want = env_int("HS_XCD_WGS_PER_CU", p->desc.dtype == HS_F16 ? per_cu : 4);
     if (want >= 1 && want < per_cu) per_cu = want;
     if (per_cu < 1) per_cu = 1;
     p->xcd_blocks = per_cu * p->n_cu;
@@ -125,6 +144,7 @@ void hs_plan_desc_init(hs_plan_desc *d) {
     d->fundamental_end = 0;
     d->max_spectra = 1024;
     d->threshold = 6.0f;
+    d->kernel = HS_KERNEL_AUTO;
 }
 
 hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
@@ -141,6 +161,7 @@ hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
     if (d.harmonics < 64 && (d.report_mask >> d.harmonics) != 0) return fail(HS_ERR_ARG, "report_mask above H");
     if (d.harmonic_mask != 0 && eligible_mask(d) == 0) return fail(HS_ERR_ARG, "harmonic_mask selects no k <= H");
     if (!(d.threshold == d.threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
+    if (d.kernel < HS_KERNEL_AUTO || d.kernel > HS_KERNEL_PLAIN) return fail(HS_ERR_ARG, "bad kernel choice");
 
     hs_plan *p = new (std::nothrow) hs_plan();
     if (!p) return fail(HS_ERR_NOMEM, "host allocation failed");
@@ -159,9 +180,11 @@ hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
     e = hipMalloc((void **)&p->norm, sizeof(hs::NormRec) * (size_t)p->max_groups);
     if (e == hipSuccess) e = hipMalloc((void **)&p->parts, sizeof(hs::StatPart) * (size_t)p->parts_cap);
     if (e == hipSuccess) e = hipMalloc((void **)&p->tickets, sizeof(uint32_t) * hs::kMaxXcd);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->prefix, sizeof(uint32_t) * ((size_t)p->max_groups + 1));
     if (e != hipSuccess) {
         if (p->norm) (void)hipFree(p->norm);
         if (p->parts) (void)hipFree(p->parts);
+        if (p->tickets) (void)hipFree(p->tickets);
         delete p;
         (void)hipGetLastError();
         return fail(HS_ERR_NOMEM, "device workspace allocation failed");
@@ -183,6 +206,7 @@ hs_status hs_plan_destroy(hs_plan *p) {
     (void)hipFree(p->norm);
     (void)hipFree(p->parts);
     (void)hipFree(p->tickets);
+    (void)hipFree(p->prefix);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
     delete p;
@@ -224,9 +248,15 @@ hs_status hs_sum_1d(hs_plan *p, const void *x, int64_t n_bins, const double *nor
     a.drift = drift;
     a.cand = nullptr;
     a.thr = p->desc.threshold;
-    dim3 grid((unsigned)((n_bins + hs::kBlock - 1) / hs::kBlock), 1);
-    hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
-    if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    const bool plain = p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && a.partial);
+    if (plain || a.partial) {
+        dim3 grid((unsigned)((n_bins + hs::kBlock - 1) / hs::kBlock), 1);
+        hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
+        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    } else {
+        s = run_persistent(p, a, 1, st);
+        if (s != HS_OK) return s;
+    }
     return mark(p, 2, st);
 }
 
@@ -272,16 +302,14 @@ hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int3
     a.cap = cand_capacity;
     a.count = cand_count;
     a.thr = p->desc.threshold;
-    hs::XcdArgs xa{};
-    xa.s = a;
-    xa.n_spectra = n_spectra;
-    xa.n_xcd = p->n_xcd;
-    xa.tickets = p->tickets;
-    e = hs::launch_zero_u32(p->tickets, p->n_xcd, st);
-    if (e != hipSuccess) return fail_hip(e, "ticket reset");
-    e = hs::launch_sum_xcd(xa, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f,
-                           p->xcd_blocks, st);
-    if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    if (p->desc.kernel == HS_KERNEL_PLAIN) {
+        dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
+        e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
+        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    } else {
+        s = run_persistent(p, a, n_spectra, st);
+        if (s != HS_OK) return s;
+    }
     return mark(p, 2, st);
 }
 

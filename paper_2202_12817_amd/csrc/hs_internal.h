@@ -77,10 +77,11 @@ struct Sum2dArgs {
 
 // Persistent XCD-aware batched harmonic sum (see hs_sum_xcd.hip).
 struct XcdArgs {
-    SumArgs s;
+    SumArgs s;                // offsets == NULL: one spectrum of s.n_bins
     int32_t n_spectra;
     int32_t n_xcd;            // virtual XCDs (work queues), >= 1
     uint32_t *tickets;        // [n_xcd] chunk counters, zero at launch
+    uint32_t *prefix;         // [n_spectra + 1] chunk prefix, written by the launch
 };
 
 hipError_t launch_stats(const StatsArgs &a, int groups, bool f16, hipStream_t st);
@@ -108,7 +109,8 @@ struct hs_plan {
     hs::NormRec *norm;           // device [max_groups]
     hs::StatPart *parts;         // device [parts_cap]
     int last_groups;             // groups written by the most recent call
-    uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the batched kernel
+    uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the persistent kernel
+    uint32_t *prefix;            // device [max_groups + 1] chunk prefix of the persistent kernel
     int n_cu, n_xcd;             // device shape
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel

@@ -1,27 +1,30 @@
-// Persistent, XCD-aware harmonic-sum kernel for batches of spectra (gfx950).
+// Persistent, XCD-aware harmonic-sum kernel (gfx950) for one spectrum or a
+// batch of spectra of any lengths.
 //
 // Why: a fundamental's k-th harmonic reads bins near k n, so over all
 // fundamentals and harmonics every cache line of a spectrum is touched about
 // once per harmonic (N H s bytes for N bins of s bytes).  Whether those
 // touches hit the XCD's 4 MB L2 or go to the Infinity Fabric depends only on
-// scheduling: if the resident workgroups of one XCD walk one contiguous block
-// of fundamentals harmonic by harmonic at the same pace, the harmonic windows
-// [k a, k (a + D)] of consecutive harmonics overlap and stay in that XCD's L2.
+// scheduling: when the resident workgroups of one XCD work on a narrow band of
+// consecutive fundamentals, the windows [k a, k (a + D)] of neighbouring
+// harmonics overlap and stay in that XCD's L2.
 //
-// How: the grid holds as many workgroups as can be resident.  Workgroup b
-// belongs to virtual XCD b % n_xcd (the hardware dispatches workgroups to XCDs
-// round robin; correctness does not depend on it).  Virtual XCD q owns the
-// spectra q, q + n_xcd, q + 2 n_xcd, ... and hands out their chunks of
-// kBlock * F consecutive fundamentals in increasing order through one atomic
-// ticket counter, so its resident workgroups always work on adjacent chunks of
-// one spectrum and progress through the harmonics together.  Every ticket
-// beyond the queue's last chunk ends the workgroup: all waves reach the exit.
+// How: every spectrum's fundamentals are cut into chunks of roughly equal
+// work (chunk size grows as the number of harmonics that fit shrinks, see
+// spec_info) and the chunks of all spectra are concatenated in order.  The
+// grid holds as many workgroups as can be resident; workgroup b serves work
+// queue b % n_xcd (the hardware dispatches workgroups to XCDs round robin;
+// correctness does not depend on it), and queue q owns the q-th of n_xcd equal
+// contiguous slices of the chunk list, handed out in order through one atomic
+// ticket counter.  So each XCD sweeps its own slice front to back with its
+// resident workgroups on adjacent chunks.  A ticket beyond the slice ends the
+// workgroup: every wave reaches the exit.
 //
-// Per lane: F fundamentals (n, n + 256, ...) walked harmonic by harmonic with
-// independent loads in flight.  The harmonic loop bound is wave-uniform (the
-// largest K of the wave); a lane whose own K is smaller issues its loads at an
-// out-of-range buffer offset, which returns zero without touching memory, and
-// commits nothing.
+// Per lane: F fundamentals (p0 + threadIdx.x + f kBlock) walked harmonic by
+// harmonic with independent loads in flight.  The harmonic loop bound is
+// wave-uniform (the largest K of the wave); a lane whose own K is smaller
+// issues its loads at an out-of-range buffer offset, which returns zero
+// without touching memory, and commits nothing.
 #include "hs_internal.h"
 
 namespace hs {
@@ -43,9 +46,15 @@ struct SpecInfo {
     uint32_t first[kClasses + 1];      // first chunk of each class
 };
 
-__device__ __forceinline__ void spec_info(SpecInfo &r, const int64_t *offsets, int s, uint32_t base, int H) {
-    r.off = offsets[s];
-    r.len = offsets[s + 1] - r.off;
+__device__ __forceinline__ void spec_info(SpecInfo &r, const int64_t *offsets, int64_t n_bins, int s, uint32_t base,
+                                          int H) {
+    if (offsets) {
+        r.off = offsets[s];
+        r.len = offsets[s + 1] - r.off;
+    } else {                                            // one spectrum of n_bins
+        r.off = 0;
+        r.len = n_bins;
+    }
     if (r.len < 0 || r.len >= (1ll << 30)) r.len = 0;   // malformed offsets: no output, no read
     const uint32_t len = (uint32_t)r.len;
     r.bound[0] = 0;
@@ -110,7 +119,7 @@ __device__ __forceinline__ void stage_push(Stage &st, const SumArgs &a, bool pre
 // p0 + f kBlock + threadIdx.x), restricted to [p0, p_end).
 template <int HMAX, bool GREEDY, bool F16, int F>
 __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInfo &si, int64_t p0, int64_t p_end,
-                                          __amdgpu_buffer_rsrc_t rsrc, const float2 *__restrict__ tab, int valid,
+                                          __amdgpu_buffer_rsrc_t rsrc, const float2 *tab, int valid,
                                           Stage &st) {
     using L = Loader<F16>;
     constexpr uint32_t eb = L::kBytes;
@@ -133,10 +142,11 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
         if (nw < a.first_bin) nw = a.first_bin;
         const int kw = valid ? keff<GREEDY>(nw, len, a.first_bin, n_end, a.H) : 0;
         KW = kw > KW ? kw : KW;
+        KW = __builtin_amdgcn_readfirstlane(KW);           // wave-uniform by construction
         m[f] = n[f];
         d[f] = 0;
         S[f] = 0.0f;
-        best[f] = 0.0f;
+        best[f] = -__builtin_inff();                       // any finite SNR beats it: first eligible k wins
         kb[f] = 0;
         db[f] = 0;
     }
@@ -173,11 +183,13 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
                     v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)o, 0, 0));
             }
             S[f] = S[f] + v;                                // + 0 on inactive lanes
-            const float snr = __builtin_fmaf(S[f], tk.x, tk.y);
-            const bool upd = act && el && (kb[f] == 0 || snr > best[f]);
-            best[f] = upd ? snr : best[f];
-            kb[f] = upd ? k : kb[f];
-            db[f] = upd ? (int)d[f] : db[f];
+            if (el) {                                       // wave-uniform
+                const float snr = __builtin_fmaf(S[f], tk.x, tk.y);
+                const bool upd = act && snr > best[f];
+                best[f] = upd ? snr : best[f];
+                kb[f] = upd ? k : kb[f];
+                db[f] = upd ? (int)d[f] : db[f];
+            }
             m[f] += n[f];
         }
     }
@@ -203,6 +215,37 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
     }
 }
 
+// Exclusive prefix of the chunk counts of all spectra (one block).
+__global__ __launch_bounds__(1024) void k_chunk_prefix(const int64_t *offsets, int64_t n_bins, int n_spectra, int H,
+                                                      uint32_t chunk, uint32_t *prefix) {
+    __shared__ uint32_t carry;
+    __shared__ uint32_t part[1024];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < n_spectra; b0 += 1024) {
+        const int s = b0 + threadIdx.x;
+        uint32_t c = 0;
+        if (s < n_spectra) {
+            SpecInfo si;
+            spec_info(si, offsets, n_bins, s, chunk, H);
+            c = si.chunks;
+        }
+        part[threadIdx.x] = c;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {               // inclusive scan
+            uint32_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (s < n_spectra) prefix[s] = carry + part[threadIdx.x] - c;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) prefix[n_spectra] = carry;
+}
+
 template <int HMAX, bool GREEDY, bool F16, int F>
 __global__ __launch_bounds__(kBlock) void k_sum_xcd(XcdArgs xa) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
@@ -211,53 +254,72 @@ __global__ __launch_bounds__(kBlock) void k_sum_xcd(XcdArgs xa) {
     const int q = blockIdx.x % xa.n_xcd;
     __shared__ uint32_t s_ticket;
     __shared__ hs_candidate s_stage[kBlock / 64][kStage];
+    __shared__ float2 s_tab[HS_MAX_HARMONICS];     // (rs_k, nm_k) of the current spectrum
     Stage st{s_stage[threadIdx.x >> 6], 0};
+    int tab_s = -1;                                 // spectrum whose table is in s_tab
 
-    int s = q;
-    uint32_t base = 0;                              // first ticket of spectrum s
+    // this queue's slice [g0, g1) of the concatenated chunk list
+    const uint32_t total = xa.prefix[xa.n_spectra];
+    const uint32_t g0 = (uint32_t)((uint64_t)total * q / xa.n_xcd);
+    const uint32_t g1 = (uint32_t)((uint64_t)total * (q + 1) / xa.n_xcd);
+    // spectrum holding chunk g0: last s with prefix[s] <= g0 (binary search, uniform)
+    int s = 0;
+    {
+        int lo = 0, hi = xa.n_spectra - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (xa.prefix[mid] <= g0) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+    }
     SpecInfo si;
-    si.chunks = 0;
-    if (s < xa.n_spectra) spec_info(si, a.offsets, s, CH, a.H);
+    spec_info(si, a.offsets, a.n_bins, s, CH, a.H);
+    uint32_t base = xa.prefix[s];                  // global index of spectrum s's first chunk
 
     if (threadIdx.x == 0) s_ticket = atomicAdd(xa.tickets + q, 1u);
     __syncthreads();
-    uint32_t t = s_ticket;
+    // readfirstlane: the ticket is block-uniform; making that visible to the
+    // compiler keeps everything derived from it (spectrum, chunk, table
+    // address) in SGPRs and the table reads scalar
+    uint32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
     for (;;) {
         __syncthreads();                            // everyone has read s_ticket
         uint32_t next = 0;
         if (threadIdx.x == 0) next = atomicAdd(xa.tickets + q, 1u);   // prefetch: used after this chunk
-        while (s < xa.n_spectra && t >= base + si.chunks) {   // advance to the spectrum holding ticket t
+        const uint32_t g = g0 + t;
+        if (g >= g1) break;                                    // slice exhausted (uniform)
+        while (g >= base + si.chunks) {                        // advance to the spectrum holding g
             base += si.chunks;
-            s += xa.n_xcd;
-            if (s < xa.n_spectra) spec_info(si, a.offsets, s, CH, a.H);
+            ++s;
+            spec_info(si, a.offsets, a.n_bins, s, CH, a.H);
         }
-        if (s >= xa.n_spectra) break;                          // queue exhausted (uniform)
-        const uint32_t c = t - base;
+        const uint32_t c = g - base;
         int j = 0;
         while (j + 1 < kClasses && c >= si.first[j + 1]) ++j;
         const int64_t lo = (int64_t)si.bound[j] + (int64_t)(c - si.first[j]) * ((int64_t)CH << j);
         int64_t hi = lo + ((int64_t)CH << j);
         if (hi > (int64_t)si.bound[j + 1]) hi = si.bound[j + 1];
-        const NormRec *nr = a.norm + s;
+        const NormRec *nr = a.norm + __builtin_amdgcn_readfirstlane(s);
         const int valid = nr->valid;
+        if (s != tab_s) {                                      // uniform: reload the table
+            if (threadIdx.x < HS_MAX_HARMONICS) s_tab[threadIdx.x] = nr->t[threadIdx.x];
+            __syncthreads();
+            tab_s = s;
+        }
         const __amdgpu_buffer_rsrc_t rsrc =
             make_rsrc((const char *)a.x + si.off * eb, (uint32_t)(si.len * eb));
         for (int64_t p0 = lo; p0 < hi; p0 += CH)
-            walk_pass<HMAX, GREEDY, F16, F>(a, s, si, p0, hi, rsrc, nr->t, valid, st);
+            walk_pass<HMAX, GREEDY, F16, F>(a, s, si, p0, hi, rsrc, s_tab, valid, st);
         if (threadIdx.x == 0) s_ticket = next;
         __syncthreads();
-        t = s_ticket;
+        t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
     if (a.cand) stage_flush(st, a);
 }
 
 template <int HMAX, bool GREEDY, bool F16>
 const void *kernel_ptr(int F) {
-    switch (F) {
-        case 1: return (const void *)k_sum_xcd<HMAX, GREEDY, F16, 1>;
-        case 2: return (const void *)k_sum_xcd<HMAX, GREEDY, F16, 2>;
-        default: return (const void *)k_sum_xcd<HMAX, GREEDY, F16, 4>;
-    }
+    return F == 2 ? (const void *)k_sum_xcd<HMAX, GREEDY, F16, 2> : (const void *)k_sum_xcd<HMAX, GREEDY, F16, 4>;
 }
 
 template <int HMAX>
@@ -282,6 +344,10 @@ hipError_t xcd_resident_blocks(int hmax, bool greedy, bool f16, int F, int *per_
 }
 
 hipError_t launch_sum_xcd(const XcdArgs &a, int hmax, bool greedy, bool f16, int F, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1024), 0, st, a.s.offsets, a.s.n_bins, a.n_spectra, a.s.H,
+                       (uint32_t)(kBlock * F), a.prefix);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     void *args[] = {(void *)&a};
     return hipLaunchKernel(xcd_kernel(hmax, greedy, f16, F), dim3(blocks), dim3(kBlock), args, 0, st);
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhs.so")
 HS_OK, HS_ERR_ARG, HS_ERR_UNSUPPORTED, HS_ERR_HIP, HS_ERR_NOMEM = 0, 1, 2, 3, 4
 HS_STANDARD, HS_GREEDY = 0, 1
 HS_F32, HS_F16 = 0, 1
+HS_KERNEL_AUTO, HS_KERNEL_PERSISTENT, HS_KERNEL_PLAIN = 0, 1, 2
 HS_MAX_HARMONICS = 32
 
 EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched",
@@ -31,7 +32,7 @@ class HsPlanDesc(ctypes.Structure):
     _fields_ = [("harmonics", ctypes.c_int32), ("mode", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("first_bin", ctypes.c_int32), ("harmonic_mask", ctypes.c_uint64),
                 ("report_mask", ctypes.c_uint64), ("fundamental_end", ctypes.c_int64),
-                ("max_spectra", ctypes.c_int32), ("threshold", ctypes.c_float)]
+                ("max_spectra", ctypes.c_int32), ("threshold", ctypes.c_float), ("kernel", ctypes.c_int32)]
 
 
 class HsCandidate(ctypes.Structure):

@@ -28,12 +28,15 @@ def _mask(ks) -> int:
     return m
 
 
+_KERNELS = {"auto": hs.HS_KERNEL_AUTO, "persistent": hs.HS_KERNEL_PERSISTENT, "plain": hs.HS_KERNEL_PLAIN}
+
+
 def make_plan(H, mode, dtype=hs.HS_F32, *, first_bin=1, harmonic_mask=0, report_mask=0, fundamental_end=0,
-              max_spectra=1, threshold=6.0) -> hs.Plan:
+              max_spectra=1, threshold=6.0, kernel="auto") -> hs.Plan:
     return hs.Plan(harmonics=int(H), mode=_MODES[mode], dtype=int(dtype), first_bin=int(first_bin),
                    harmonic_mask=int(harmonic_mask), report_mask=int(report_mask),
                    fundamental_end=int(fundamental_end), max_spectra=int(max_spectra),
-                   threshold=float(threshold))
+                   threshold=float(threshold), kernel=_KERNELS[kernel])
 
 
 def _norm_tensor(norm, n, device):
@@ -46,13 +49,13 @@ def _norm_tensor(norm, n, device):
 
 
 def sum_1d(x: torch.Tensor, H: int, mode="greedy", *, first_bin=1, harmonic_mask=0, fundamental_end=0,
-           report=(), norm=None, plan: hs.Plan | None = None, stream=None, with_norm=False):
+           report=(), norm=None, plan: hs.Plan | None = None, stream=None, with_norm=False, kernel="auto"):
     """Dense harmonic sum of one spectrum; returns snr/harm/drift (+ partial, norm)."""
     n = x.numel()
     own = plan is None
     if own:
         plan = make_plan(H, mode, _dtype_code(x), first_bin=first_bin, harmonic_mask=harmonic_mask,
-                         report_mask=_mask(report), fundamental_end=fundamental_end)
+                         report_mask=_mask(report), fundamental_end=fundamental_end, kernel=kernel)
     dev = x.device
     snr = torch.empty(n, dtype=torch.float32, device=dev)
     harm = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -80,14 +83,14 @@ def get_norm(plan: hs.Plan, n: int, H: int, device, stream=None):
 
 def sum_batched(x: torch.Tensor, offsets: torch.Tensor, H: int, mode="greedy", threshold=6.0, *, first_bin=1,
                 harmonic_mask=0, fundamental_end=0, dense=False, candidates=True, capacity=None, norm=None,
-                plan: hs.Plan | None = None, stream=None, with_norm=False):
+                plan: hs.Plan | None = None, stream=None, with_norm=False, kernel="auto"):
     """Batch of spectra ``x[offsets[s]:offsets[s+1]]``; candidates and/or dense outputs."""
     B = offsets.numel() - 1
     dev = x.device
     own = plan is None
     if own:
         plan = make_plan(H, mode, _dtype_code(x), first_bin=first_bin, harmonic_mask=harmonic_mask,
-                         fundamental_end=fundamental_end, max_spectra=B, threshold=threshold)
+                         fundamental_end=fundamental_end, max_spectra=B, threshold=threshold, kernel=kernel)
     out = {}
     snr = harm = drift = cand = count = None
     if dense:

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     from paper_2202_12817_amd import hs
     assert ctypes.sizeof(hs.HsCandidate) == 16
-    assert ctypes.sizeof(hs.HsPlanDesc) == 48
+    assert ctypes.sizeof(hs.HsPlanDesc) == 56
 
 
 def test_desc_defaults(lib):
@@ -50,12 +50,12 @@ def test_desc_defaults(lib):
     d = hs.hs_plan_desc_init()
     assert (d.harmonics, d.mode, d.dtype, d.first_bin) == (32, hs.HS_GREEDY, hs.HS_F32, 1)
     assert d.harmonic_mask == 0 and d.report_mask == 0 and d.fundamental_end == 0
-    assert d.max_spectra == 1024 and d.threshold == pytest.approx(6.0)
+    assert d.max_spectra == 1024 and d.threshold == pytest.approx(6.0) and d.kernel == hs.HS_KERNEL_AUTO
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("harmonics", 0, 1), ("harmonics", 33, 2), ("mode", 7, 1), ("dtype", 5, 1), ("first_bin", 0, 1),
-    ("max_spectra", 0, 1), ("max_spectra", 70000, 1), ("fundamental_end", -1, 1),
+    ("max_spectra", 0, 1), ("max_spectra", 70000, 1), ("fundamental_end", -1, 1), ("kernel", 3, 1),
 ])
 def test_plan_create_rejects_bad_desc(lib, field, value, status):
     from paper_2202_12817_amd import hs

@@ -92,15 +92,16 @@ def test_config1_standard_and_greedy_with_partials(dev):
 SIZES = [2, 3, 5, 255, 256, 257, 1000, 4099, 65537, 300001]
 
 
+@pytest.mark.parametrize("kernel", ["persistent", "plain"])
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
-def test_1d_sizes_and_ragged_tails(dev, n, mode):
+def test_1d_sizes_and_ragged_tails(dev, n, mode, kernel):
     x = synthetic.exp_noise(n, 100 + n)
     for H in (1, 3, 8, 17, 32):
-        print("1d", n, mode, H, flush=True)
-        got = _ops().sum_1d(torch.from_numpy(x).to(dev), H, mode, with_norm=n > 2)
+        print("1d", kernel, n, mode, H, flush=True)
+        got = _ops().sum_1d(torch.from_numpy(x).to(dev), H, mode, with_norm=n > 2, kernel=kernel)
         check_dense(got, oracle.hs_1d(x, H, MODES[mode]), oracle.hs_1d(x, H, MODES[mode], precision="f64"),
-                    "n=%d H=%d %s" % (n, H, mode))
+                    "n=%d H=%d %s %s" % (n, H, mode, kernel))
 
 
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
@@ -158,10 +159,14 @@ def test_1d_degenerate_spectrum_gives_zeros(dev):
 def test_config2_full_size(dev, mode):
     x, _ = synthetic.config2()
     print("config2", mode, flush=True)
-    got = _ops().sum_1d(torch.from_numpy(x).to(dev), 32, mode, with_norm=True)
+    xt = torch.from_numpy(x).to(dev)
+    got = _ops().sum_1d(xt, 32, mode, with_norm=True)
     check_dense(got, oracle.hs_1d(x, 32, MODES[mode]), oracle.hs_1d(x, 32, MODES[mode], precision="f64"),
                 "config2 " + mode)
     check_norm(got, x, 1, 32, "config2")
+    plain = _ops().sum_1d(xt, 32, mode, kernel="plain")
+    for k in ("snr", "harm", "drift"):
+        assert torch.equal(plain[k], got[k]), k
 
 
 def test_1d_deterministic(dev):
@@ -215,9 +220,10 @@ def _same_records(a, b):
         np.array_equal(a["snr"].view(np.uint32), b["snr"].view(np.uint32))
 
 
+@pytest.mark.parametrize("kernel", ["persistent", "plain"])
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
 @pytest.mark.parametrize("f16", [False, True])
-def test_batched_small(dev, mode, f16):
+def test_batched_small(dev, mode, f16, kernel):
     B = 37
     x, off = synthetic.config3(n_spectra=B, lo=2, hi=90000, seed=61)
     thr = 4.0
@@ -229,7 +235,7 @@ def test_batched_small(dev, mode, f16):
     ot = torch.from_numpy(off).to(dev)
     print("batched", mode, f16, flush=True)
     got = _ops().sum_batched(xt, ot, 32, mode, thr, dense=True, candidates=True, capacity=x.size,
-                             with_norm=True)
+                             with_norm=True, kernel=kernel)
     w = oracle.hs_batched(x, off, 32, MODES[mode], thr, dense=True)
     ms = _np(got["mu_sigma"])
     for s in range(B):
