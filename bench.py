@@ -24,6 +24,72 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 H = 32
 THRESHOLD = 6.0
+SUM_KERNEL = "k_sum_xcd<32, true, false, 4>"          # dominant kernel (FP32 greedy, 4 fundamentals/lane)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sum_xcd_batched_512x_h32_greedy_f32.txt")
+CALIB_BYTES = 1 << 30
+
+
+def source_hash():
+    """Hash of the HIP sources: a traffic figure is valid only for the kernel it was taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2202_12817_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 summary, or None."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("json: "):
+                rec = json.loads(line[6:])
+                if rec.get("source") == source_hash():
+                    return rec["fetch_bytes"] + rec["write_bytes"]
+    except OSError:
+        pass
+    return None
+
+
+def pmc_summary(dirs):
+    """Summarise rocprofv3 --pmc CSV output (FETCH_SIZE, WRITE_SIZE runs) into per-dispatch bytes.
+
+    Each counter is scaled by what it reads for the calibration kernel (an
+    elementwise negation that reads and writes CALIB_BYTES, run in the same
+    process)."""
+    import csv
+    import glob
+    out = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            per = {}
+            for r in csv.DictReader(open(f)):
+                key = (r["Kernel_Name"], r["Counter_Name"])
+                per.setdefault(key, []).append(float(r["Counter_Value"]))
+            for (kname, cname), vals in per.items():
+                out.setdefault(cname, {})[kname] = vals
+    lines = []
+    rec = {"kernel": SUM_KERNEL, "source": source_hash()}
+    for cname, key in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
+        kern = out.get(cname, {})
+        copy = [v for k, vs in kern.items() if "neg" in k for v in vs]
+        calib = max(copy) if copy else None
+        scale = CALIB_BYTES / (calib * 1024.0) if calib else None
+        lines.append("%s: calibration copy of %d bytes reads %s KiB -> scale %s" % (
+            cname, CALIB_BYTES, "%.1f" % calib if calib else "n/a", "%.4f" % scale if scale else "n/a"))
+        for k, vs in sorted(kern.items()):
+            if "hs::" not in k:
+                continue
+            avg = sum(vs) / len(vs)
+            lines.append("  %-70s dispatches %3d  avg %12.1f KiB  scaled %14.0f bytes" % (
+                k[:70], len(vs), avg, avg * 1024.0 * (scale or 1.0)))
+            if "k_sum_xcd<32, true, false, 4>" in k:
+                rec[key] = avg * 1024.0 * (scale or 1.0)
+    lines.append("json: " + json.dumps(rec))
+    return "\n".join(lines)
 
 
 def keff_sum(lengths, H, greedy, first_bin=1):
@@ -48,7 +114,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and FP16 legs")
     ap.add_argument("--cpu-sample", type=int, default=24, help="spectra in the CPU oracle sample")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run a 1 GiB read + 1 GiB write elementwise kernel (reference for rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                    help="summarise rocprofv3 --pmc CSV directories and exit (no GPU work)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the harmonic-sum library runs on a single device "
               "(independent spectra shard across GPUs by the caller); run with --gpus 1", file=sys.stderr)
@@ -121,14 +194,24 @@ def main():
         "hbm_gbs_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9,
         "hbm_frac_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "stage_ms": {"normalisation": norm_avg_ms, "harmonic_sum": sum_avg_ms},
-        "roofline": {"bound": "hbm", "kernel": "k_sum_1d<32,greedy,f32>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": SUM_KERNEL, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": read_traffic()},
     }
+
+    if args.calibration_copy:
+        # an elementwise negation reads and writes CALIB_BYTES once; its kernel
+        # name ("neg") identifies it in the counter output
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     if not args.no_extra:
         # plain: one hs_sum_1d per spectrum, dense outputs, no graph
-        pplan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, threshold=THRESHOLD)
+        pplan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, threshold=THRESHOLD,
+                        kernel=hs.HS_KERNEL_PLAIN)
         nmax = int(lengths.max())
         snr = torch.empty(nmax, dtype=torch.float32, device=dev)
         harm = torch.empty(nmax, dtype=torch.uint8, device=dev)

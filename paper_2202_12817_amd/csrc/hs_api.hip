@@ -119,8 +119,8 @@ hs_status setup_xcd(hs_plan *p) {
     int per_cu = 0;
     e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f, &per_cu);
     if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    // measured on MI355X (512 spectra, H = 32): FP32 is fastest at 4 resident
-    // workgroups per CU (more in flight thrashes the XCD's L2), FP16 at full occupancy
+    // at most 4 resident workgroups per CU (the kernel is compiled for <= 4 waves
+    // per SIMD so that it never spills); measured fastest at 4 for FP32 and FP16
     int want = env_int("HS_XCD_WGS_PER_CU", p->desc.dtype == HS_F16 ? per_cu : 4);
     if (want >= 1 && want < per_cu) per_cu = want;
     if (per_cu < 1) per_cu = 1;

@@ -246,8 +246,11 @@ __global__ __launch_bounds__(1024) void k_chunk_prefix(const int64_t *offsets, i
     if (threadIdx.x == 0) prefix[n_spectra] = carry;
 }
 
+// At most 4 waves per SIMD (4 resident workgroups per CU): lets the compiler
+// use up to 128 VGPRs, so the unrolled harmonic loop never spills (with the
+// default occupancy target it capped VGPRs at 64 and spilled to scratch).
 template <int HMAX, bool GREEDY, bool F16, int F>
-__global__ __launch_bounds__(kBlock) void k_sum_xcd(XcdArgs xa) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_sum_xcd(XcdArgs xa) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
     constexpr int CH = kBlock * F;                 // fundamentals per pass (class-0 chunk)
     const SumArgs &a = xa.s;
