@@ -13,6 +13,7 @@ plus the CPU oracle on a bounded sample of the same workload.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 H = 32
 THRESHOLD = 6.0
-SUM_KERNEL = "k_sum_xcd<32, true, false, 4>"          # dominant kernel (FP32 greedy, 4 fundamentals/lane)
+SUM_KERNEL = "k_sum_xcd<32, true, false, %d>"         # dominant kernel (FP32 greedy; fundamentals per lane)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sum_xcd_batched_512x_h32_greedy_f32.txt")
 CALIB_BYTES = 1 << 30
 
@@ -41,15 +42,15 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(kernel):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 summary, or None."""
     try:
         for line in open(TRAFFIC_FILE):
             if line.startswith("json: "):
                 rec = json.loads(line[6:])
-                if rec.get("source") == source_hash():
+                if rec.get("source") == source_hash() and rec.get("kernel") == kernel:
                     return rec["fetch_bytes"] + rec["write_bytes"]
-    except OSError:
+    except (OSError, KeyError, ValueError):
         pass
     return None
 
@@ -59,7 +60,8 @@ def pmc_summary(dirs):
 
     Each counter is scaled by what it reads for the calibration kernel (an
     elementwise negation that reads and writes CALIB_BYTES, run in the same
-    process)."""
+    process).  One ``json:`` line per batched FP32 greedy harmonic-sum kernel
+    found (one per launch shape profiled)."""
     import csv
     import glob
     out = {}
@@ -70,9 +72,9 @@ def pmc_summary(dirs):
                 key = (r["Kernel_Name"], r["Counter_Name"])
                 per.setdefault(key, []).append(float(r["Counter_Value"]))
             for (kname, cname), vals in per.items():
-                out.setdefault(cname, {})[kname] = vals
+                out.setdefault(cname, {}).setdefault(kname, []).extend(vals)
     lines = []
-    rec = {"kernel": SUM_KERNEL, "source": source_hash()}
+    recs = {}
     for cname, key in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
         kern = out.get(cname, {})
         copy = [v for k, vs in kern.items() if "neg" in k for v in vs]
@@ -86,9 +88,12 @@ def pmc_summary(dirs):
             avg = sum(vs) / len(vs)
             lines.append("  %-70s dispatches %3d  avg %12.1f KiB  scaled %14.0f bytes" % (
                 k[:70], len(vs), avg, avg * 1024.0 * (scale or 1.0)))
-            if "k_sum_xcd<32, true, false, 4>" in k:
-                rec[key] = avg * 1024.0 * (scale or 1.0)
-    lines.append("json: " + json.dumps(rec))
+            m = re.search(r"k_sum_xcd<32, true, false, (\d)>", k)
+            if m:
+                name = SUM_KERNEL % int(m.group(1))
+                recs.setdefault(name, {"kernel": name, "source": source_hash()})[key] = avg * 1024.0 * (scale or 1.0)
+    for rec in recs.values():
+        lines.append("json: " + json.dumps(rec))
     return "\n".join(lines)
 
 
@@ -105,6 +110,58 @@ def keff_sum(lengths, H, greedy, first_bin=1):
     return total
 
 
+def keff_sum_2d(n_r, z_min, z_max, H, greedy, first_bin=1):
+    """Sum of K_eff over the f-fdot plane (row z truncates at the first harmonic row outside the plane)."""
+    total = 0
+    for z in range(z_min, z_max + 1):
+        kz = H if z == 0 else (z_max // z if z > 0 else z_min // z)
+        for k in range(1, min(H, kz) + 1):
+            hi = (n_r - 1) // k - (1 if greedy else 0)
+            if hi >= first_bin:
+                total += min(hi, n_r - 1) - first_bin + 1
+    return total
+
+
+def plane_2d_leg(hs, torch, dev, steps, warmup):
+    """The f-fdot plane (2^21 columns x 201 rows, z = -100..100, H = 16, dense outputs)."""
+    import synthetic
+    plane, _ = synthetic.config4(threads=16)
+    n_z, n_r = plane.shape
+    z_min, z_max, h2 = -100, 100, 16
+    p32 = torch.from_numpy(plane).to(dev)
+    p16 = torch.empty(plane.shape, dtype=torch.int16, device=dev)
+    scale = float(np.float32(plane.mean(dtype=np.float64)))
+    hs.hs_quantize_f16(p32, plane.size, scale, p16)
+    del plane
+    snr = torch.empty((n_z, n_r), dtype=torch.float32, device=dev)
+    harm = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
+    drift = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
+    out = {"workload": "f-fdot plane %d x %d (z = %d..%d), H=%d, dense snr/harm/drift" % (n_r, n_z, z_min, z_max, h2)}
+    for dname, dt, pin, eb in (("f32", hs.HS_F32, p32, 4), ("f16", hs.HS_F16, p16, 2)):
+        for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
+            plan = hs.Plan(harmonics=h2, mode=mode, dtype=dt)
+            for _ in range(warmup):
+                hs.hs_sum_2d(plan.handle, pin, n_r, n_r, z_min, z_max, None, snr, harm, drift)
+            torch.cuda.synchronize()
+            hs.hs_plan_set_timing(plan.handle, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                hs.hs_sum_2d(plan.handle, pin, n_r, n_r, z_min, z_max, None, snr, harm, drift)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            c, nm, sm = hs.hs_plan_get_timing(plan.handle)
+            plan.close()
+            work = keff_sum_2d(n_r, z_min, z_max, h2, mode == hs.HS_GREEDY)
+            comp = n_z * n_r * (eb + 6)
+            sum_ms = sm / max(1, c)
+            out["%s_%s" % (dname, mname)] = {
+                "value": work / el, "unit": "bin·harmonics/s", "ms_per_step": 1e3 * el,
+                "stage_ms": {"normalisation": nm / max(1, c), "harmonic_sum": sum_ms},
+                "sum_kernel_gbs_compulsory": comp / (sum_ms * 1e-3) / 1e9,
+                "sum_kernel_frac_compulsory": comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +171,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and FP16 legs")
     ap.add_argument("--cpu-sample", type=int, default=24, help="spectra in the CPU oracle sample")
+    ap.add_argument("--tune-cache", default=None, help="launch-shape cache file of the tuner (default: tune afresh)")
+    ap.add_argument("--launch", default=None, metavar="F,W",
+                    help="fixed launch shape (fundamentals per lane, workgroups per CU) instead of tuning")
+    ap.add_argument("--plane-2d", action="store_true", help="also time the f-fdot plane (2^21 x 201, H=16)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a 1 GiB read + 1 GiB write elementwise kernel (reference for rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
@@ -150,6 +211,14 @@ def main():
     def step(p, xin):
         hs.hs_sum_batched(p.handle, xin, ot, B, None, None, None, None, cand, cap, count, stream)
 
+    # launch shape of the persistent kernel: tuned on this batch (the tuner
+    # times every shape; results do not depend on it)
+    if args.launch:
+        hs.hs_plan_set_launch(plan.handle, *[int(v) for v in args.launch.split(",")])
+    else:
+        hs.hs_plan_tune_batched(plan.handle, xt, ot, B, None, None, None, None, cand, cap, count, args.tune_cache,
+                                stream)
+    shape = hs.hs_plan_get_launch(plan.handle)
     for _ in range(args.warmup):
         step(plan, xt)
     torch.cuda.synchronize()
@@ -163,6 +232,17 @@ def main():
     calls, norm_ms, sum_ms = hs.hs_plan_get_timing(plan.handle)
     hs.hs_plan_set_timing(plan.handle, False)
     n_cand = int(count.item())
+    # the same step replayed as one captured hipGraph per call
+    hs.hs_plan_set_graph(plan.handle, True)
+    step(plan, xt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(plan, xt)
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    graph_info = hs.hs_plan_graph_info(plan.handle)
+    hs.hs_plan_set_graph(plan.handle, False)
     ms_step = 1e3 * elapsed / args.steps
     value = work * args.steps / elapsed
 
@@ -194,9 +274,12 @@ def main():
         "hbm_gbs_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9,
         "hbm_frac_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "stage_ms": {"normalisation": norm_avg_ms, "harmonic_sum": sum_avg_ms},
-        "roofline": {"bound": "hbm", "kernel": SUM_KERNEL, "achieved": achieved,
+        "launch": {"fundamentals_per_lane": shape[0], "workgroups_per_cu": shape[1], "tuned": not args.launch},
+        "graph_replay": {"ms_per_step": graph_ms, "value": work / (graph_ms * 1e-3),
+                         "graphs_recorded": graph_info[0], "replays": graph_info[1]},
+        "roofline": {"bound": "hbm", "kernel": SUM_KERNEL % shape[0], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic()},
+                     "traffic": read_traffic(SUM_KERNEL % shape[0])},
     }
 
     if args.calibration_copy:
@@ -258,6 +341,9 @@ def main():
                                   "stage_ms": {"normalisation": n16 / max(1, c16), "harmonic_sum": s16 / max(1, c16)},
                                   "candidates": n_cand16}
         del x16
+
+    if args.plane_2d:
+        result["plane_2d"] = plane_2d_leg(hs, torch, dev, args.steps, args.warmup)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -67,11 +67,15 @@ typedef enum hs_status {
 
 enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
 enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
-/* hs_plan_desc.kernel: which 1D kernel runs.  AUTO = PERSISTENT except when
+/* hs_plan_desc.kernel: which kernel runs.  AUTO = PERSISTENT except when
  * partial sums are reported (hs_sum_1d with report_mask), which uses PLAIN.
  * PLAIN is the design the paper describes for its GPU sum (Sec. 3.1.1): one
- * thread per fundamental bin, a grid per spectrum.  PERSISTENT is the
- * XCD-aware work-queue kernel (same results, bit for bit). */
+ * thread per fundamental bin, a grid per spectrum (per plane row in 2D).
+ * PERSISTENT is, in 1D, the XCD-aware work-queue kernel and, in 2D, the
+ * ray-tiled kernel that stages each tile's window of the plane in LDS (used
+ * when a tile of ratio width 1 fits its budget: up to about 126 rows on each
+ * side of z = 0; wider planes run PLAIN).  All give the same results, bit for
+ * bit. */
 enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
 
 #define HS_MAX_HARMONICS 32
@@ -190,6 +194,55 @@ hs_status hs_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out,
  */
 hs_status hs_plan_set_timing(hs_plan *plan, int32_t enable);
 hs_status hs_plan_get_timing(hs_plan *plan, int32_t *calls, double *norm_ms, double *sum_ms);
+
+/*
+ * Graph capture.  Every sum entry point enqueues kernels only (no memset, no
+ * copy, no allocation, no synchronisation), so a caller may record it into
+ * its own graph with stream capture; each replay then reuses the plan's
+ * workspace, so replays through one plan must not overlap on the GPU.  Stage
+ * timing must be off while the caller's stream captures (HS_ERR_ARG).
+ *
+ * hs_plan_set_graph(plan, 1) makes the library do this itself: the first
+ * call with a given argument set (entry point, every pointer and size) is
+ * recorded into a hipGraph and every later call with the same arguments
+ * replays it with one graph launch on the caller's stream (the same results:
+ * the graph holds the same kernels).  The 8 most recently used argument sets
+ * are kept; dropping one waits for its last replay.  Timed calls and calls on
+ * a capturing stream run without the cache.  Disabling (0) waits for the last
+ * replay of every cached graph and releases them.  hs_plan_graph_info returns
+ * the number of recorded graphs and of replays since the plan was created.
+ */
+hs_status hs_plan_set_graph(hs_plan *plan, int32_t enable);
+hs_status hs_plan_graph_info(hs_plan *plan, int64_t *captures, int64_t *replays);
+
+/*
+ * Launch shape of the persistent kernel (hs_sum_batched and the persistent
+ * hs_sum_1d): fundamentals per lane (2 or 4) and resident workgroups of 256
+ * threads per CU (1..4, bounded by the kernel's occupancy).  The results do
+ * not depend on the shape.  Default: 4 and the occupancy limit (environment
+ * HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan creation).
+ * Setting a new shape drops the plan's cached graphs.
+ */
+hs_status hs_plan_set_launch(hs_plan *plan, int32_t fundamentals_per_lane, int32_t workgroups_per_cu);
+hs_status hs_plan_get_launch(hs_plan *plan, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu);
+
+/*
+ * Autotuner of the launch shape for a batch (arguments as hs_sum_batched; the
+ * work of Sec. 4.3 is batches of many spectra, whose best shape depends on
+ * the device and on the batch).  Runs hs_sum_batched once with the current
+ * shape, then, unless cache_path names a file with an entry for this key,
+ * times every shape (one warm-up and the median of three calls each), keeps
+ * the fastest on the plan and appends a line to cache_path (if not NULL).
+ * The key is: device architecture, CU and XCD counts, harmonic bucket, mode,
+ * dtype, output kind, and the powers of two below the total bins and the
+ * number of spectra.  On return the outputs hold the result of a complete
+ * call.  Synchronises the stream (host-blocking); HS_ERR_ARG for a plan with
+ * HS_KERNEL_PLAIN, with timing enabled, or on a capturing stream.
+ */
+hs_status hs_plan_tune_batched(hs_plan *plan, const void *x, const int64_t *offsets, int32_t n_spectra,
+                               const double *norm, float *snr, uint8_t *harm, uint8_t *drift,
+                               hs_candidate *cand, int64_t cand_capacity,
+                               unsigned long long *cand_count, const char *cache_path, void *stream);
 
 const char *hs_status_string(hs_status status);
 const char *hs_last_error(void);

@@ -101,6 +101,8 @@ int env_int(const char *name, int dflt) {
     return v && *v ? atoi(v) : dflt;
 }
 
+hs_status resident_limit(hs_plan *p, int F, int *per_cu);
+
 // Shape of the persistent batched launch: one work queue per XCD, as many
 // workgroups as are resident.  HS_XCD_F and HS_XCD_WGS_PER_CU override the
 // defaults (tuning aids).
@@ -117,14 +119,420 @@ hs_status setup_xcd(hs_plan *p) {
     int F = env_int("HS_XCD_F", 4);
     p->xcd_f = (F == 2 || F == 4) ? F : 4;
     int per_cu = 0;
-    e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, p->xcd_f, &per_cu);
-    if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    // at most 4 resident workgroups per CU (the kernel is compiled for <= 4 waves
-    // per SIMD so that it never spills); measured fastest at 4 for FP32 and FP16
-    int want = env_int("HS_XCD_WGS_PER_CU", p->desc.dtype == HS_F16 ? per_cu : 4);
+    hs_status s = resident_limit(p, p->xcd_f, &per_cu);
+    if (s != HS_OK) return s;
+    // default: as many workgroups as are resident (measured fastest for FP32
+    // and FP16 on the 512-spectrum batch); hs_plan_tune_batched searches
+    int want = env_int("HS_XCD_WGS_PER_CU", per_cu);
     if (want >= 1 && want < per_cu) per_cu = want;
-    if (per_cu < 1) per_cu = 1;
     p->xcd_blocks = per_cu * p->n_cu;
+    // window elements per tile of the ray-tiled plane kernel (HS_RAY_BUDGET
+    // overrides: 256..15360, so that the staged window stays below 64 KiB)
+    const int rb = env_int("HS_RAY_BUDGET", hs::kRayBudget);
+    p->ray_budget = rb >= 256 && rb <= 15360 ? rb : hs::kRayBudget;
+    return HS_OK;
+}
+
+// Launch sequences of the sum entry points (arguments already validated).
+hs_status enqueue_1d(hs_plan *p, const void *x, int64_t n_bins, const double *norm, float *snr, uint8_t *harm,
+                     uint8_t *drift, float *partial, hipStream_t st) {
+    hs::StatsArgs sa{};
+    sa.x = x;
+    sa.offsets = nullptr;
+    sa.n_bins = n_bins;
+    sa.rows = 1;
+    sa.row_len = n_bins;
+    sa.stride = n_bins;
+    sa.first_bin = p->desc.first_bin;
+    sa.chunks = hs::kChunks1D;
+    sa.user_norm = norm;
+    hs_status s = run_norm(p, sa, 1, st);
+    if (s != HS_OK) return s;
+    hs::SumArgs a{};
+    a.x = x;
+    a.offsets = nullptr;
+    a.n_bins = n_bins;
+    a.norm = p->norm;
+    a.first_bin = p->desc.first_bin;
+    a.H = p->desc.harmonics;
+    a.n_end = n_end_of(p->desc, n_bins);
+    a.kmask = eligible_mask(p->desc);
+    a.report_mask = partial ? p->desc.report_mask : 0;
+    a.partial = p->desc.report_mask ? partial : nullptr;
+    a.snr = snr;
+    a.harm = harm;
+    a.drift = drift;
+    a.cand = nullptr;
+    a.thr = p->desc.threshold;
+    const bool plain = p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && a.partial);
+    if (plain || a.partial) {
+        dim3 grid((unsigned)((n_bins + hs::kBlock - 1) / hs::kBlock), 1);
+        hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
+        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    } else {
+        s = run_persistent(p, a, 1, st);
+        if (s != HS_OK) return s;
+    }
+    return mark(p, 2, st);
+}
+
+hs_status enqueue_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra, const double *norm,
+                          float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
+                          unsigned long long *cand_count, hipStream_t st) {
+    hipError_t e;
+    if (cand) {
+        e = hs::launch_zero_u64(cand_count, st);
+        if (e != hipSuccess) return fail_hip(e, "counter reset");
+    }
+    hs::StatsArgs sa{};
+    sa.x = x;
+    sa.offsets = offsets;
+    sa.rows = 1;
+    sa.first_bin = p->desc.first_bin;
+    sa.chunks = hs::kChunksBatched;
+    sa.user_norm = norm;
+    hs_status s = run_norm(p, sa, n_spectra, st);
+    if (s != HS_OK) return s;
+    hs::SumArgs a{};
+    a.x = x;
+    a.offsets = offsets;
+    a.n_bins = 0;
+    a.norm = p->norm;
+    a.first_bin = p->desc.first_bin;
+    a.H = p->desc.harmonics;
+    a.n_end = p->desc.fundamental_end > 0 ? p->desc.fundamental_end : (1ll << 62);
+    a.kmask = eligible_mask(p->desc);
+    a.report_mask = 0;
+    a.partial = nullptr;
+    a.snr = snr;
+    a.harm = harm;
+    a.drift = drift;
+    a.cand = cand;
+    a.cap = cand_capacity;
+    a.count = cand_count;
+    a.thr = p->desc.threshold;
+    if (p->desc.kernel == HS_KERNEL_PLAIN) {
+        dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
+        e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
+        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    } else {
+        s = run_persistent(p, a, n_spectra, st);
+        if (s != HS_OK) return s;
+    }
+    return mark(p, 2, st);
+}
+
+hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stride, int32_t z_min, int32_t z_max,
+                     const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
+                     int64_t cand_capacity, unsigned long long *cand_count, hipStream_t st) {
+    const int64_t n_z = (int64_t)z_max - z_min + 1;
+    hipError_t e;
+    if (cand) {
+        e = hs::launch_zero_u64(cand_count, st);
+        if (e != hipSuccess) return fail_hip(e, "counter reset");
+    }
+    hs::StatsArgs sa{};
+    sa.x = plane;
+    sa.offsets = nullptr;
+    sa.n_bins = n_r;
+    sa.rows = n_z;
+    sa.row_len = n_r;
+    sa.stride = row_stride;
+    sa.first_bin = p->desc.first_bin;
+    sa.chunks = hs::kChunks2D;
+    sa.user_norm = norm;
+    hs_status s = run_norm(p, sa, 1, st);
+    if (s != HS_OK) return s;
+    hs::Sum2dArgs a{};
+    a.row0 = 0;
+    a.plane = plane;
+    a.n_r = n_r;
+    a.stride = row_stride;
+    a.z_min = z_min;
+    a.z_max = z_max;
+    a.norm = p->norm;
+    a.first_bin = p->desc.first_bin;
+    a.H = p->desc.harmonics;
+    a.n_end = n_end_of(p->desc, n_r);
+    a.kmask = eligible_mask(p->desc);
+    a.snr = snr;
+    a.harm = harm;
+    a.drift = drift;
+    a.cand = cand;
+    a.cap = cand_capacity;
+    a.count = cand_count;
+    a.thr = p->desc.threshold;
+    const bool greedy = p->desc.mode == HS_GREEDY, f16 = p->desc.dtype == HS_F16;
+    hs::RayGeom g{};
+    g.n_r = n_r;
+    g.u_lo[0] = z_min > 1 ? z_min : 1;
+    g.u_hi[0] = z_max;
+    g.u_lo[1] = -z_max > 1 ? -z_max : 1;
+    g.u_hi[1] = -z_min;
+    g.budget = p->ray_budget;
+    if (p->desc.kernel != HS_KERNEL_PLAIN && hs::ray_feasible(g)) {
+        hs::Ray2dArgs ra{};
+        ra.s = a;
+        ra.g = g;
+        ra.bands = p->ray;
+        ra.n_xcd = p->n_xcd;
+        e = hs::launch_sum_2d_ray(ra, p->hmax, greedy, f16, st);
+        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel (ray tiles)");
+        if (z_min <= 0 && z_max >= 0) {   // row z = 0
+            a.row0 = -z_min;
+            e = hs::launch_sum_2d(a, p->hmax, greedy, f16, 1, st);
+        }
+    } else {
+        e = hs::launch_sum_2d(a, p->hmax, greedy, f16, (int)n_z, st);
+    }
+    if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    return mark(p, 2, st);
+}
+
+uint64_t W(const void *ptr) { return (uint64_t)(uintptr_t)ptr; }
+
+constexpr size_t kGraphCache = 8;   // captured argument sets kept per plan
+
+hs_status release_graph(hs_plan::GraphEntry &g) {
+    hipError_t e = hipEventSynchronize(g.done);
+    if (e == hipSuccess) e = hipGraphExecDestroy(g.exec);
+    if (e == hipSuccess) e = hipEventDestroy(g.done);
+    return e == hipSuccess ? HS_OK : fail_hip(e, "graph release");
+}
+
+hs_status clear_graphs(hs_plan *p) {
+    hs_status s = HS_OK;
+    for (auto &g : p->graphs) {
+        hs_status r = release_graph(g);
+        if (s == HS_OK) s = r;
+    }
+    p->graphs.clear();
+    return s;
+}
+
+// Record one call (body) into a new graph of the plan's cache.
+template <class Body>
+hs_status capture(hs_plan *p, std::vector<uint64_t> &&key, Body &body, hs_plan::GraphEntry **out) {
+    hipError_t e;
+    if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamCreateWithFlags");
+    }
+    if (p->graphs.size() >= kGraphCache) {
+        size_t lru = 0;
+        for (size_t i = 1; i < p->graphs.size(); ++i)
+            if (p->graphs[i].last_use < p->graphs[lru].last_use) lru = i;
+        hs_status s = release_graph(p->graphs[lru]);
+        p->graphs.erase(p->graphs.begin() + lru);
+        if (s != HS_OK) return s;
+    }
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
+    hs_status s = body(p->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (s != HS_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s != HS_OK ? s : fail_hip(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+    hipEvent_t done = nullptr;
+    e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return fail_hip(e, "hipEventCreate");
+    }
+    p->graphs.push_back(hs_plan::GraphEntry{std::move(key), exec, done, 0});
+    *out = &p->graphs.back();
+    ++p->captures;
+    return HS_OK;
+}
+
+// Run one validated sum call: directly, or (graph mode) as a replay of the
+// graph captured for the same arguments.  Calls made while the caller's
+// stream is itself capturing, and timed calls, run directly (a timed call on
+// a capturing stream is refused: its events would time nothing).
+template <class Body>
+hs_status dispatch(hs_plan *p, std::vector<uint64_t> &&key, hipStream_t st, Body body) {
+    if (!p->graph && !p->timing) return body(st);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) {
+        if (p->timing) return fail(HS_ERR_ARG, "stage timing is enabled while the stream is capturing");
+        return body(st);
+    }
+    if (p->timing) return body(st);
+    hs_plan::GraphEntry *g = nullptr;
+    for (auto &c : p->graphs)
+        if (c.key == key) {
+            g = &c;
+            break;
+        }
+    if (g) {
+        ++p->replays;
+    } else {
+        hs_status s = capture(p, std::move(key), body, &g);
+        if (s != HS_OK) return s;
+    }
+    g->last_use = ++p->graph_clock;
+    e = hipGraphLaunch(g->exec, st);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    e = hipEventRecord(g->done, st);
+    if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    return HS_OK;
+}
+
+// Largest workgroups per CU of the persistent kernel with F fundamentals per
+// lane (it is compiled for at most 4 waves per SIMD, i.e. 4 workgroups of 256).
+hs_status resident_limit(hs_plan *p, int F, int *per_cu) {
+    hipError_t e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, F, per_cu);
+    if (e != hipSuccess) return fail_hip(e, "occupancy query");
+    if (*per_cu > 4) *per_cu = 4;
+    if (*per_cu < 1) *per_cu = 1;
+    return HS_OK;
+}
+
+hs_status set_shape(hs_plan *p, int F, int wgs_per_cu) {
+    if (F != 2 && F != 4) return fail(HS_ERR_ARG, "fundamentals per lane must be 2 or 4");
+    int lim = 0;
+    hs_status s = resident_limit(p, F, &lim);
+    if (s != HS_OK) return s;
+    if (wgs_per_cu < 1 || wgs_per_cu > lim) return fail(HS_ERR_ARG, "workgroups per CU out of range");
+    if (F != p->xcd_f || wgs_per_cu * p->n_cu != p->xcd_blocks) {
+        s = clear_graphs(p);   // captured launches hold the old shape
+        if (s != HS_OK) return s;
+    }
+    p->xcd_f = F;
+    p->xcd_blocks = wgs_per_cu * p->n_cu;
+    return HS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape tuner of the persistent kernel.  Every shape gives the same
+// results bit for bit; only the time differs.  A cache file holds one JSON
+// object per line: {"key": "...", "fundamentals_per_lane": F,
+// "workgroups_per_cu": W, "ms": t}.
+// ---------------------------------------------------------------------------
+
+std::string tune_key(hs_plan *p, int64_t total_bins, int32_t n_spectra, bool dense, bool cand) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        size_t c = arch.find(':');
+        if (c != std::string::npos) arch.resize(c);
+    } else {
+        (void)hipGetLastError();
+    }
+    int lg = 0;
+    while (lg < 62 && (1ll << (lg + 1)) <= total_bins) ++lg;
+    int ls = 0;
+    while (ls < 30 && (1 << (ls + 1)) <= n_spectra) ++ls;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s cu%d xcd%d h%d %s %s %s%s bins2^%d spectra2^%d", arch.c_str(), p->n_cu, p->n_xcd,
+             p->hmax, p->desc.mode == HS_GREEDY ? "greedy" : "standard", p->desc.dtype == HS_F16 ? "f16" : "f32",
+             dense ? "dense" : "", cand ? "+cand" : "", lg, ls);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int *F, int *Wg) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, pat.c_str())) continue;
+        const char *a = strstr(line, "\"fundamentals_per_lane\":");
+        const char *b = strstr(line, "\"workgroups_per_cu\":");
+        if (!a || !b) continue;
+        *F = atoi(a + strlen("\"fundamentals_per_lane\":"));
+        *Wg = atoi(b + strlen("\"workgroups_per_cu\":"));
+        found = true;   // the last matching line wins
+    }
+    fclose(f);
+    return found;
+}
+
+hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra, const double *norm,
+                       float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
+                       unsigned long long *cand_count, const char *cache_path, hipStream_t st) {
+    if (p->desc.kernel == HS_KERNEL_PLAIN) return fail(HS_ERR_ARG, "the plan uses the plain kernel: nothing to tune");
+    auto call = [&]() {
+        return hs_sum_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                              (void *)st);
+    };
+    hs_status s = call();   // validates the arguments and warms up
+    if (s != HS_OK) return s;
+    int64_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, offsets + n_spectra, sizeof total, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e, "reading the batch size");
+    const std::string key = tune_key(p, total, n_spectra, snr != nullptr, cand != nullptr);
+    int F = 0, Wg = 0;
+    if (cache_path && cache_lookup(cache_path, key, &F, &Wg) && set_shape(p, F, Wg) == HS_OK) return HS_OK;
+
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    const int F0 = p->xcd_f, W0 = p->xcd_blocks / p->n_cu;
+    int bestF = F0, bestW = W0;
+    float best = 3.4e38f;
+    for (int f : {2, 4}) {
+        int lim = 0;
+        s = resident_limit(p, f, &lim);
+        if (s != HS_OK) break;
+        for (int w = 1; w <= lim && s == HS_OK; ++w) {
+            s = set_shape(p, f, w);
+            if (s == HS_OK) s = call();   // warm-up of this shape
+            float t[3];
+            for (int r = 0; r < 3 && s == HS_OK; ++r) {
+                e = hipEventRecord(t0, st);
+                if (e != hipSuccess) {
+                    s = fail_hip(e, "hipEventRecord");
+                    break;
+                }
+                s = call();
+                if (s != HS_OK) break;
+                e = hipEventRecord(t1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t[r], t0, t1);
+                if (e != hipSuccess) s = fail_hip(e, "timing a tuning run");
+            }
+            if (s != HS_OK) break;
+            float med = t[0] < t[1] ? (t[1] < t[2] ? t[1] : (t[0] < t[2] ? t[2] : t[0]))
+                                    : (t[0] < t[2] ? t[0] : (t[1] < t[2] ? t[2] : t[1]));
+            if (med < best) {
+                best = med;
+                bestF = f;
+                bestW = w;
+            }
+        }
+        if (s != HS_OK) break;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (s != HS_OK) {
+        (void)set_shape(p, F0, W0);
+        return s;
+    }
+    s = set_shape(p, bestF, bestW);
+    if (s != HS_OK) return s;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (!f) return fail(HS_ERR_ARG, "cannot append to the tuning cache file");
+        fprintf(f, "{\"key\": \"%s\", \"fundamentals_per_lane\": %d, \"workgroups_per_cu\": %d, \"ms\": %.4f}\n",
+                key.c_str(), bestF, bestW, best);
+        fclose(f);
+    }
     return HS_OK;
 }
 
@@ -181,10 +589,12 @@ hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
     if (e == hipSuccess) e = hipMalloc((void **)&p->parts, sizeof(hs::StatPart) * (size_t)p->parts_cap);
     if (e == hipSuccess) e = hipMalloc((void **)&p->tickets, sizeof(uint32_t) * hs::kMaxXcd);
     if (e == hipSuccess) e = hipMalloc((void **)&p->prefix, sizeof(uint32_t) * ((size_t)p->max_groups + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->ray, sizeof(hs::RayBand) * hs::kRayMaxBands);
     if (e != hipSuccess) {
         if (p->norm) (void)hipFree(p->norm);
         if (p->parts) (void)hipFree(p->parts);
         if (p->tickets) (void)hipFree(p->tickets);
+        if (p->prefix) (void)hipFree(p->prefix);
         delete p;
         (void)hipGetLastError();
         return fail(HS_ERR_NOMEM, "device workspace allocation failed");
@@ -207,7 +617,10 @@ hs_status hs_plan_destroy(hs_plan *p) {
     (void)hipFree(p->parts);
     (void)hipFree(p->tickets);
     (void)hipFree(p->prefix);
+    (void)hipFree(p->ray);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    (void)clear_graphs(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipSetDevice(cur);
     delete p;
     return HS_OK;
@@ -220,44 +633,8 @@ hs_status hs_sum_1d(hs_plan *p, const void *x, int64_t n_bins, const double *nor
     if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
     if (p->desc.report_mask != 0 && !partial) return fail(HS_ERR_ARG, "report_mask set but partial is NULL");
     hipStream_t st = (hipStream_t)stream;
-    hs::StatsArgs sa{};
-    sa.x = x;
-    sa.offsets = nullptr;
-    sa.n_bins = n_bins;
-    sa.rows = 1;
-    sa.row_len = n_bins;
-    sa.stride = n_bins;
-    sa.first_bin = p->desc.first_bin;
-    sa.chunks = hs::kChunks1D;
-    sa.user_norm = norm;
-    hs_status s = run_norm(p, sa, 1, st);
-    if (s != HS_OK) return s;
-    hs::SumArgs a{};
-    a.x = x;
-    a.offsets = nullptr;
-    a.n_bins = n_bins;
-    a.norm = p->norm;
-    a.first_bin = p->desc.first_bin;
-    a.H = p->desc.harmonics;
-    a.n_end = n_end_of(p->desc, n_bins);
-    a.kmask = eligible_mask(p->desc);
-    a.report_mask = partial ? p->desc.report_mask : 0;
-    a.partial = p->desc.report_mask ? partial : nullptr;
-    a.snr = snr;
-    a.harm = harm;
-    a.drift = drift;
-    a.cand = nullptr;
-    a.thr = p->desc.threshold;
-    const bool plain = p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && a.partial);
-    if (plain || a.partial) {
-        dim3 grid((unsigned)((n_bins + hs::kBlock - 1) / hs::kBlock), 1);
-        hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
-        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
-    } else {
-        s = run_persistent(p, a, 1, st);
-        if (s != HS_OK) return s;
-    }
-    return mark(p, 2, st);
+    return dispatch(p, {1, W(x), (uint64_t)n_bins, W(norm), W(snr), W(harm), W(drift), W(partial)}, st,
+                    [=](hipStream_t s) { return enqueue_1d(p, x, n_bins, norm, snr, harm, drift, partial, s); });
 }
 
 hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra, const double *norm,
@@ -270,47 +647,13 @@ hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int3
     if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
     if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (cand) {
-        e = hs::launch_zero_u64(cand_count, st);
-        if (e != hipSuccess) return fail_hip(e, "counter reset");
-    }
-    hs::StatsArgs sa{};
-    sa.x = x;
-    sa.offsets = offsets;
-    sa.rows = 1;
-    sa.first_bin = p->desc.first_bin;
-    sa.chunks = hs::kChunksBatched;
-    sa.user_norm = norm;
-    hs_status s = run_norm(p, sa, n_spectra, st);
-    if (s != HS_OK) return s;
-    hs::SumArgs a{};
-    a.x = x;
-    a.offsets = offsets;
-    a.n_bins = 0;
-    a.norm = p->norm;
-    a.first_bin = p->desc.first_bin;
-    a.H = p->desc.harmonics;
-    a.n_end = p->desc.fundamental_end > 0 ? p->desc.fundamental_end : (1ll << 62);
-    a.kmask = eligible_mask(p->desc);
-    a.report_mask = 0;
-    a.partial = nullptr;
-    a.snr = snr;
-    a.harm = harm;
-    a.drift = drift;
-    a.cand = cand;
-    a.cap = cand_capacity;
-    a.count = cand_count;
-    a.thr = p->desc.threshold;
-    if (p->desc.kernel == HS_KERNEL_PLAIN) {
-        dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
-        e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
-        if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
-    } else {
-        s = run_persistent(p, a, n_spectra, st);
-        if (s != HS_OK) return s;
-    }
-    return mark(p, 2, st);
+    return dispatch(p,
+                    {2, W(x), W(offsets), (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
+                     (uint64_t)cand_capacity, W(cand_count)},
+                    st, [=](hipStream_t s) {
+                        return enqueue_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity,
+                                               cand_count, s);
+                    });
 }
 
 hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stride, int32_t z_min, int32_t z_max,
@@ -328,49 +671,14 @@ hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stri
     if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
     if (cand && n_z * n_r > 0xffffffffll) return fail(HS_ERR_UNSUPPORTED, "plane too large for 32-bit candidate bins");
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (cand) {
-        e = hs::launch_zero_u64(cand_count, st);
-        if (e != hipSuccess) return fail_hip(e, "counter reset");
-    }
-    hs::StatsArgs sa{};
-    sa.x = plane;
-    sa.offsets = nullptr;
-    sa.n_bins = n_r;
-    sa.rows = n_z;
-    sa.row_len = n_r;
-    sa.stride = row_stride;
-    sa.first_bin = p->desc.first_bin;
-    sa.chunks = hs::kChunks2D;
-    sa.user_norm = norm;
-    // rows == 1 is the 1D layout; keep the plane description for one row too
-    if (n_z == 1) {
-        sa.rows = 1;
-        sa.n_bins = n_r;
-    }
-    hs_status s = run_norm(p, sa, 1, st);
-    if (s != HS_OK) return s;
-    hs::Sum2dArgs a{};
-    a.plane = plane;
-    a.n_r = n_r;
-    a.stride = row_stride;
-    a.z_min = z_min;
-    a.z_max = z_max;
-    a.norm = p->norm;
-    a.first_bin = p->desc.first_bin;
-    a.H = p->desc.harmonics;
-    a.n_end = n_end_of(p->desc, n_r);
-    a.kmask = eligible_mask(p->desc);
-    a.snr = snr;
-    a.harm = harm;
-    a.drift = drift;
-    a.cand = cand;
-    a.cap = cand_capacity;
-    a.count = cand_count;
-    a.thr = p->desc.threshold;
-    e = hs::launch_sum_2d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, st);
-    if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
-    return mark(p, 2, st);
+    return dispatch(p,
+                    {3, W(plane), (uint64_t)n_r, (uint64_t)row_stride, (uint64_t)(uint32_t)z_min,
+                     (uint64_t)(uint32_t)z_max, W(norm), W(snr), W(harm), W(drift), W(cand), (uint64_t)cand_capacity,
+                     W(cand_count)},
+                    st, [=](hipStream_t s) {
+                        return enqueue_2d(p, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand,
+                                          cand_capacity, cand_count, s);
+                    });
 }
 
 hs_status hs_get_norm(hs_plan *p, int32_t n, double *mu_sigma, float *tables, int32_t *valid, void *stream) {
@@ -418,6 +726,50 @@ hs_status hs_plan_get_timing(hs_plan *p, int32_t *calls, double *norm_ms, double
     if (sum_ms) *sum_ms = b;
     p->ev_used = 0;
     return HS_OK;
+}
+
+hs_status hs_plan_set_graph(hs_plan *p, int32_t enable) {
+    if (!p) return fail(HS_ERR_ARG, "null plan");
+    p->graph = enable != 0;
+    return p->graph ? HS_OK : clear_graphs(p);
+}
+
+hs_status hs_plan_graph_info(hs_plan *p, int64_t *captures, int64_t *replays) {
+    if (!p) return fail(HS_ERR_ARG, "null plan");
+    if (captures) *captures = p->captures;
+    if (replays) *replays = p->replays;
+    return HS_OK;
+}
+
+hs_status hs_plan_set_launch(hs_plan *p, int32_t fundamentals_per_lane, int32_t workgroups_per_cu) {
+    if (!p) return fail(HS_ERR_ARG, "null plan");
+    return set_shape(p, fundamentals_per_lane, workgroups_per_cu);
+}
+
+hs_status hs_plan_get_launch(hs_plan *p, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu) {
+    if (!p) return fail(HS_ERR_ARG, "null plan");
+    if (fundamentals_per_lane) *fundamentals_per_lane = p->xcd_f;
+    if (workgroups_per_cu) *workgroups_per_cu = p->xcd_blocks / p->n_cu;
+    return HS_OK;
+}
+
+hs_status hs_plan_tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra,
+                               const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
+                               int64_t cand_capacity, unsigned long long *cand_count, const char *cache_path,
+                               void *stream) {
+    if (!p) return fail(HS_ERR_ARG, "null plan");
+    if (p->timing) return fail(HS_ERR_ARG, "stage timing is enabled");
+    hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(HS_ERR_ARG, "the stream is capturing");
+    const bool graph = p->graph;
+    p->graph = false;
+    hs_status s = tune_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                               cache_path, st);
+    p->graph = graph;
+    return s;
 }
 
 const char *hs_status_string(hs_status s) {

@@ -57,6 +57,7 @@ struct SumArgs {
 
 // Harmonic sum over an f-fdot plane.
 struct Sum2dArgs {
+    int32_t row0;             // plain kernel: first plane row of the launch (blockIdx.y = row - row0)
     const void *plane;
     int64_t n_r;
     int64_t stride;
@@ -84,6 +85,74 @@ struct XcdArgs {
     uint32_t *prefix;         // [n_spectra + 1] chunk prefix, written by the launch
 };
 
+// Ray-tiled f-fdot plane (see hs_sum_2d_ray.hip).  Rows z != 0 form two
+// sides (z > 0 and z < 0) of rows u = |z| in [u_lo, u_hi]; a tile of a side
+// is a ratio range [r0, r0 + delta) and holds the fundamentals (u, r) with
+// u r0 <= r < u (r0 + delta); its harmonics read row m = k u only at columns
+// [m r0, m (r0 + delta)], so the tile's window of rows u_lo..b is staged once.
+constexpr int kRayBudget = 8192;     // window elements staged per tile (default)
+constexpr int kRayMaxBands = 512;    // bands of both sides (a band: tiles with the same top row b)
+
+struct RayGeom {
+    int64_t n_r;
+    int32_t u_lo[2], u_hi[2];   // side 0: z = +u, side 1: z = -u; u_lo > u_hi: empty side
+    int32_t budget;             // window elements per tile
+};
+
+struct RayBand {
+    uint32_t first_tile;        // tiles of the band: [first_tile, first_tile + tiles)
+    int32_t side;
+    int32_t b;                  // highest window row of the band's tiles
+    int32_t delta;              // tile width (ratio units)
+    int64_t start, end;         // ratio range of the band
+};
+
+__host__ __device__ inline int64_t tri(int64_t x) { return x * (x + 1) / 2; }
+
+__host__ __device__ inline int ray_side_bands(const RayGeom &g, int side) {
+    return g.u_lo[side] <= g.u_hi[side] ? g.u_hi[side] - g.u_lo[side] + 1 : 0;
+}
+
+// Band j of a side (top row b = u_hi - j): ratio range and tile width; returns
+// the number of tiles (0 for an empty band).  Band b covers the ratios whose
+// highest non-empty window row is b: ratios r0 with floor((n_r - 1) / r0) = b
+// (for b = u_hi: every r0 <= (n_r - 1) / u_hi, including 0).
+__host__ __device__ inline uint32_t ray_band(const RayGeom &g, int side, int j, int64_t *start, int64_t *end,
+                                             int32_t *delta) {
+    const int64_t lo = g.u_lo[side], hi = g.u_hi[side], b = hi - j;
+    const int64_t rho_end = (g.n_r + lo - 1) / lo;   // every column r < n_r of every row u >= lo
+    const int64_t s = b == hi ? 0 : (g.n_r - 1) / (b + 1) + 1;
+    int64_t e = (g.n_r - 1) / b + 1;
+    if (e > rho_end) e = rho_end;
+    const int64_t rows = b - lo + 1, t = tri(b) - tri(lo - 1);
+    int64_t d = (g.budget - rows) / t;
+    if (d < 1) d = 1;
+    *start = s;
+    *end = e;
+    *delta = (int32_t)d;
+    return s < e ? (uint32_t)((e - s + d - 1) / d) : 0u;
+}
+
+// Every tile's window fits the budget (a tile of width 1 of the widest band).
+__host__ __device__ inline bool ray_feasible(const RayGeom &g) {
+    for (int side = 0; side < 2; ++side) {
+        if (g.u_lo[side] > g.u_hi[side]) continue;
+        const int64_t lo = g.u_lo[side], hi = g.u_hi[side];
+        if (tri(hi) - tri(lo - 1) + (hi - lo + 1) > g.budget) return false;
+    }
+    return ray_side_bands(g, 0) + ray_side_bands(g, 1) <= kRayMaxBands;
+}
+
+struct Ray2dArgs {
+    Sum2dArgs s;
+    RayGeom g;
+    RayBand *bands;             // [n_bands], written by the band kernel of the same launch sequence
+    int32_t n_bands;
+    uint32_t n_tiles;
+    int32_t n_xcd;              // tile ranges: XCD q owns tiles [q per_xcd, (q + 1) per_xcd)
+    uint32_t per_xcd;
+};
+
 hipError_t launch_stats(const StatsArgs &a, int groups, bool f16, hipStream_t st);
 hipError_t launch_finalize(const StatsArgs &a, int groups, hipStream_t st);
 hipError_t launch_export_norm(const NormRec *norm, int n, int H, double *mu_sigma, float *tables,
@@ -94,7 +163,8 @@ hipError_t xcd_resident_blocks(int hmax, bool greedy, bool f16, int F, int *per_
 hipError_t launch_sum_xcd(const XcdArgs &a, int hmax, bool greedy, bool f16, int F, int blocks, hipStream_t st);
 hipError_t launch_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out, hipStream_t st);
 hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3 grid, hipStream_t st);
-hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, hipStream_t st);
+hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st);
+hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, hipStream_t st);
 
 }  // namespace hs
 
@@ -111,10 +181,27 @@ struct hs_plan {
     int last_groups;             // groups written by the most recent call
     uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the persistent kernel
     uint32_t *prefix;            // device [max_groups + 1] chunk prefix of the persistent kernel
+    hs::RayBand *ray;            // device [kRayMaxBands] band table of the ray-tiled plane kernel
     int n_cu, n_xcd;             // device shape
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel
+    int ray_budget;              // window elements per tile of the ray-tiled plane kernel
     bool timing;                 // record stage events on every call
     std::vector<hipEvent_t> ev;  // 3 events per timed call: start, after norm, after sum
     int ev_used;                 // events of timed calls not yet read
+
+    // Whole-call hipGraph replay: each distinct argument set of a sum call is
+    // captured once (on cap_stream, which only records) and replayed on the
+    // caller's stream afterwards.
+    struct GraphEntry {
+        std::vector<uint64_t> key;  // entry point and every argument of the call
+        hipGraphExec_t exec;
+        hipEvent_t done;            // recorded after the latest replay
+        uint64_t last_use;
+    };
+    bool graph;
+    hipStream_t cap_stream;
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock;
+    int64_t captures, replays;
 };

@@ -17,13 +17,6 @@
 namespace hs {
 namespace {
 
-// Result of one fundamental.
-struct Best {
-    float snr;
-    int harm;
-    int drift;
-};
-
 // Harmonic walk of fundamental n of one spectrum (descriptor r); K harmonics.
 // REPORT: also store S_k for the k in report_mask (slot-major, stride pstride).
 template <int HMAX, bool GREEDY, bool F16, bool REPORT>
@@ -65,30 +58,6 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
         m += n;
     }
     return Best{kb ? best : 0.0f, kb, db};
-}
-
-// Candidate compaction of one wave: ballot, one atomic per wave, mbcnt rank.
-__device__ __forceinline__ void emit_candidate(bool pred, uint32_t spectrum, uint32_t bin, const Best &b,
-                                               hs_candidate *cand, int64_t cap, unsigned long long *count) {
-    const uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    const int lane = __lane_id();
-    const int leader = __builtin_ctzll(mask);
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(count, (unsigned long long)__builtin_popcountll(mask));
-    base = __shfl(base, leader);
-    if (pred) {
-        const unsigned long long slot = base + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-        if ((int64_t)slot < cap) {
-            hs_candidate c;
-            c.spectrum = spectrum;
-            c.bin = bin;
-            c.snr = b.snr;
-            c.harm = (uint16_t)b.harm;
-            c.drift = (uint16_t)b.drift;
-            cand[slot] = c;
-        }
-    }
 }
 
 // 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock
@@ -137,12 +106,12 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     }
 }
 
-// f-fdot plane: blockIdx.y = row i (z = z_min + i), blockIdx.x = column tile.
+// f-fdot plane: blockIdx.y = row i - row0 (z = z_min + i), blockIdx.x = column tile.
 template <int HMAX, bool GREEDY, bool F16>
 __global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
     using L = Loader<F16>;
     constexpr uint32_t eb = L::kBytes;
-    const int i = blockIdx.y;
+    const int i = a.row0 + (int)blockIdx.y;
     const int z = a.z_min + i;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool in = r < a.n_r;
@@ -243,9 +212,8 @@ hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3
     }
 }
 
-hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, hipStream_t st) {
-    const int64_t n_z = (int64_t)a.z_max - a.z_min + 1;
-    dim3 grid((unsigned)((a.n_r + kBlock - 1) / kBlock), (unsigned)n_z);
+hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st) {
+    dim3 grid((unsigned)((a.n_r + kBlock - 1) / kBlock), (unsigned)rows);
     switch (hmax) {
         case 4: return sum2d_h<4>(a, greedy, f16, grid, st);
         case 8: return sum2d_h<8>(a, greedy, f16, grid, st);

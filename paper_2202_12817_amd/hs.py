@@ -25,7 +25,8 @@ HS_MAX_HARMONICS = 32
 
 EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched",
             "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
-            "hs_status_string", "hs_last_error"]
+            "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
+            "hs_plan_tune_batched", "hs_status_string", "hs_last_error"]
 
 
 class HsPlanDesc(ctypes.Structure):
@@ -71,12 +72,19 @@ def load(path: str = LIB_PATH):
         lib.hs_quantize_f16.argtypes = [vp, i64, ctypes.c_float, vp, vp]
         lib.hs_plan_set_timing.argtypes = [vp, i32]
         lib.hs_plan_get_timing.argtypes = [vp, vp, vp, vp]
+        lib.hs_plan_set_graph.argtypes = [vp, i32]
+        lib.hs_plan_graph_info.argtypes = [vp, vp, vp]
+        lib.hs_plan_set_launch.argtypes = [vp, i32, i32]
+        lib.hs_plan_get_launch.argtypes = [vp, vp, vp]
+        lib.hs_plan_tune_batched.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, i64, vp, ctypes.c_char_p, vp]
         lib.hs_status_string.argtypes = [ctypes.c_int]
         lib.hs_status_string.restype = ctypes.c_char_p
         lib.hs_last_error.argtypes = []
         lib.hs_last_error.restype = ctypes.c_char_p
         for name in ("hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d",
-                     "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing"):
+                     "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
+                     "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
+                     "hs_plan_tune_batched"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -166,6 +174,36 @@ def hs_plan_get_timing(plan):
     c, a, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
     _check(load().hs_plan_get_timing(plan, ctypes.byref(c), ctypes.byref(a), ctypes.byref(b)), "hs_plan_get_timing")
     return c.value, a.value, b.value
+
+
+def hs_plan_set_graph(plan, enable: bool) -> None:
+    _check(load().hs_plan_set_graph(plan, 1 if enable else 0), "hs_plan_set_graph")
+
+
+def hs_plan_graph_info(plan):
+    """(graphs recorded, replays) since the plan was created."""
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().hs_plan_graph_info(plan, ctypes.byref(c), ctypes.byref(r)), "hs_plan_graph_info")
+    return c.value, r.value
+
+
+def hs_plan_set_launch(plan, fundamentals_per_lane: int, workgroups_per_cu: int) -> None:
+    _check(load().hs_plan_set_launch(plan, int(fundamentals_per_lane), int(workgroups_per_cu)), "hs_plan_set_launch")
+
+
+def hs_plan_get_launch(plan):
+    """(fundamentals per lane, workgroups per CU) of the persistent kernel."""
+    f, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().hs_plan_get_launch(plan, ctypes.byref(f), ctypes.byref(w)), "hs_plan_get_launch")
+    return f.value, w.value
+
+
+def hs_plan_tune_batched(plan, x, offsets, n_spectra, norm, snr, harm, drift, cand=None, cand_capacity=0,
+                         cand_count=None, cache_path=None, stream=None):
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(load().hs_plan_tune_batched(plan, _p(x), _p(offsets), int(n_spectra), _p(norm), _p(snr), _p(harm),
+                                       _p(drift), _p(cand), int(cand_capacity), _p(cand_count), path,
+                                       _stream(stream)), "hs_plan_tune_batched")
 
 
 def hs_status_string(status: int) -> str:

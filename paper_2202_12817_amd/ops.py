@@ -116,7 +116,7 @@ def sum_batched(x: torch.Tensor, offsets: torch.Tensor, H: int, mode="greedy", t
 
 def sum_2d(plane: torch.Tensor, z_min: int, z_max: int, H: int, mode="greedy", *, first_bin=1, harmonic_mask=0,
            fundamental_end=0, dense=True, candidates=False, threshold=6.0, capacity=None, norm=None,
-           plan: hs.Plan | None = None, stream=None, with_norm=False):
+           plan: hs.Plan | None = None, stream=None, with_norm=False, kernel="auto"):
     """f-fdot plane [n_z, n_r] (row stride from the tensor); dense planes and/or candidates."""
     n_z, n_r = plane.shape
     if n_z != z_max - z_min + 1:
@@ -127,7 +127,7 @@ def sum_2d(plane: torch.Tensor, z_min: int, z_max: int, H: int, mode="greedy", *
     own = plan is None
     if own:
         plan = make_plan(H, mode, _dtype_code(plane), first_bin=first_bin, harmonic_mask=harmonic_mask,
-                         fundamental_end=fundamental_end, threshold=threshold)
+                         fundamental_end=fundamental_end, threshold=threshold, kernel=kernel)
     out = {}
     snr = harm = drift = cand = count = None
     if dense:

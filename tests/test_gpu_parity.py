@@ -15,12 +15,12 @@ import pytest
 
 import oracle
 import synthetic
+from gpu_checks import TOL, _cands, _np, _same_records, check_dense, check_norm  # noqa: F401
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 MODES = {"standard": oracle.STANDARD, "greedy": oracle.GREEDY}
-TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -35,35 +35,6 @@ def dev():
 def _ops():
     from paper_2202_12817_amd import ops
     return ops
-
-
-def _np(t):
-    return t.cpu().numpy()
-
-
-def check_dense(got, want32, want64, label=""):
-    harm, drift, snr = _np(got["harm"]).reshape(-1), _np(got["drift"]).reshape(-1), _np(got["snr"]).reshape(-1)
-    wh, wd, ws = want32["harm"].reshape(-1), want32["drift"].reshape(-1), want32["snr"].reshape(-1)
-    bad = np.flatnonzero((harm != wh) | (drift != wd))
-    assert bad.size == 0, "%s: %d index mismatches, first at %s: gpu (%d,%d) oracle (%d,%d)" % (
-        label, bad.size, bad[:5], harm[bad[0]], drift[bad[0]], wh[bad[0]], wd[bad[0]])
-    sb = np.flatnonzero(snr.view(np.uint32) != ws.view(np.uint32))
-    assert sb.size == 0, "%s: %d SNR values differ from the float mirror, first %s: %r vs %r" % (
-        label, sb.size, sb[:5], snr[sb[0]], ws[sb[0]])
-    if want64 is not None:
-        s64 = want64["snr"].reshape(-1)
-        err = np.abs(snr.astype(np.float64) - s64) / np.maximum(1.0, np.abs(s64))
-        assert float(err.max(initial=0.0)) <= TOL, "%s: SNR error %.3g" % (label, float(err.max()))
-
-
-def check_norm(got, x, first_bin, H, label=""):
-    mu1, sigma1 = oracle.norm_from_data(x, first_bin)
-    ms = _np(got["mu_sigma"])[0]
-    assert ms[0] == mu1 and ms[1] == sigma1, "%s: stats (%r, %r) vs oracle (%r, %r)" % (
-        label, ms[0], ms[1], mu1, sigma1)
-    _, _, rs, nm = oracle.tables(mu1, sigma1, H)
-    tab = _np(got["tables"])[0]
-    assert np.array_equal(tab[0], rs) and np.array_equal(tab[1], nm), label
 
 
 # ---------------------------------------------------------------------------
@@ -207,19 +178,6 @@ def test_fp16_storage_sums(dev, mode):
 # batched
 # ---------------------------------------------------------------------------
 
-def _cands(out):
-    recs, n = _ops().candidates_numpy(out)
-    recs = np.sort(recs, order=["spectrum", "bin"])
-    return recs, n
-
-
-def _same_records(a, b):
-    if a.size != b.size:
-        return False
-    return all(np.array_equal(a[f], b[f]) for f in ("spectrum", "bin", "harm", "drift")) and \
-        np.array_equal(a["snr"].view(np.uint32), b["snr"].view(np.uint32))
-
-
 @pytest.mark.parametrize("kernel", ["persistent", "plain"])
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
 @pytest.mark.parametrize("f16", [False, True])
@@ -325,6 +283,46 @@ def test_2d_dense(dev, mode, shape):
         check_dense(got, oracle.hs_2d(p, z_min, z_max, H, MODES[mode]),
                     oracle.hs_2d(p, z_min, z_max, H, MODES[mode], precision="f64"), "2d %s %s" % (mode, shape))
         check_norm(got, p, 1, H, "2d")
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+@pytest.mark.parametrize("shape", [(-20, 20, 20011), (-100, 100, 3001), (3, 11, 9000), (-13, -1, 7001),
+                                   (-2, 30, 12007), (-126, 126, 700), (-130, 130, 300), (-1, 1, 65537)])
+@pytest.mark.parametrize("opts", [{}, {"first_bin": 5, "fundamental_end": 1700, "harmonic_mask": 0b1010101010}])
+def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
+    """The ray-tiled plane kernel (default) against the one-thread-per-fundamental kernel,
+    bit for bit, and against the oracle; z ranges of one side, both sides, beyond the
+    tile budget (the default falls back to the plain kernel) and a ragged last tile."""
+    z_min, z_max, n_r = shape
+    p = _plane(z_max - z_min + 1, n_r, n_r + 3)
+    pt = torch.from_numpy(p).to(dev)
+    H = 16
+    print("2d ray", mode, shape, opts, flush=True)
+    got = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size, **opts)
+    ref = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size,
+                        kernel="plain", **opts)
+    for k in ("harm", "drift"):
+        assert torch.equal(got[k], ref[k]), k
+    assert torch.equal(got["snr"].view(torch.int32), ref["snr"].view(torch.int32))
+    ra, na = _cands(got)
+    rb, nb = _cands(ref)
+    assert na == nb and _same_records(ra, rb)
+    if p.size <= 2_000_000:
+        w = oracle.hs_2d(p, z_min, z_max, H, MODES[mode], **opts)
+        check_dense(got, w, None, "2d ray %s %s" % (mode, shape))
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+def test_2d_fp16_storage(dev, mode):
+    z_min, z_max, n_r = -9, 9, 30011
+    p = _plane(z_max - z_min + 1, n_r, 77)
+    q = oracle.quantize_f16(p.reshape(-1), np.float32(1.0)).reshape(p.shape)
+    dec = q.astype(np.float32)
+    pt = torch.from_numpy(q.view(np.int16)).to(dev).view(torch.float16)
+    got = _ops().sum_2d(pt, z_min, z_max, 16, mode, with_norm=True)
+    check_dense(got, oracle.hs_2d(dec, z_min, z_max, 16, MODES[mode]),
+                oracle.hs_2d(dec, z_min, z_max, 16, MODES[mode], precision="f64"), "2d fp16 " + mode)
+    check_norm(got, dec, 1, 16, "2d fp16")
 
 
 def test_2d_strided_rows_and_candidates(dev):
