@@ -67,15 +67,15 @@ typedef enum hs_status {
 
 enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
 enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
-/* hs_plan_desc.kernel: which kernel runs.  AUTO = PERSISTENT except when
- * partial sums are reported (hs_sum_1d with report_mask), which uses PLAIN.
- * PLAIN is the design the paper describes for its GPU sum (Sec. 3.1.1): one
- * thread per fundamental bin, a grid per spectrum (per plane row in 2D).
- * PERSISTENT is, in 1D, the XCD-aware work-queue kernel and, in 2D, the
- * ray-tiled kernel that stages each tile's window of the plane in LDS (used
- * when a tile of ratio width 1 fits its budget: up to about 126 rows on each
- * side of z = 0; wider planes run PLAIN).  All give the same results, bit for
- * bit. */
+/* hs_plan_desc.kernel: which kernel runs.  PLAIN is the design the paper
+ * describes for its GPU sum (Sec. 3.1.1): one thread per fundamental bin, a
+ * grid per spectrum (per plane row in 2D).  PERSISTENT is, in 1D, the
+ * XCD-aware work-queue kernel and, in 2D, the ray-tiled kernel that stages
+ * each tile's window of the plane in LDS (used when a tile of ratio width 1
+ * fits its budget, about 100 rows on each side of z = 0; wider planes run
+ * PLAIN).  AUTO = PERSISTENT in 1D except when partial sums are reported
+ * (hs_sum_1d with report_mask), and PLAIN in 2D.  All give the same results,
+ * bit for bit. */
 enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
 
 #define HS_MAX_HARMONICS 32

@@ -126,10 +126,10 @@ hs_status setup_xcd(hs_plan *p) {
     int want = env_int("HS_XCD_WGS_PER_CU", per_cu);
     if (want >= 1 && want < per_cu) per_cu = want;
     p->xcd_blocks = per_cu * p->n_cu;
-    // window elements per tile of the ray-tiled plane kernel (HS_RAY_BUDGET
-    // overrides: 256..15360, so that the staged window stays below 64 KiB)
-    const int rb = env_int("HS_RAY_BUDGET", hs::kRayBudget);
-    p->ray_budget = rb >= 256 && rb <= 15360 ? rb : hs::kRayBudget;
+    // LDS bytes of a tile's window in the ray-tiled plane kernel (HS_RAY_LDS
+    // overrides: 4096..61440, so that window and staging stay below 64 KiB)
+    const int rl = env_int("HS_RAY_LDS", hs::kRayLdsBytes);
+    p->ray_lds = rl >= 4096 && rl <= 61440 ? rl : hs::kRayLdsBytes;
     return HS_OK;
 }
 
@@ -269,8 +269,8 @@ hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_str
     g.u_hi[0] = z_max;
     g.u_lo[1] = -z_max > 1 ? -z_max : 1;
     g.u_hi[1] = -z_min;
-    g.budget = p->ray_budget;
-    if (p->desc.kernel != HS_KERNEL_PLAIN && hs::ray_feasible(g)) {
+    g.budget = hs::ray_budget_for(p->ray_lds, greedy);
+    if (p->desc.kernel == HS_KERNEL_PERSISTENT && hs::ray_feasible(g)) {
         hs::Ray2dArgs ra{};
         ra.s = a;
         ra.g = g;

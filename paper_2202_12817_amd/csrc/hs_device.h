@@ -197,4 +197,40 @@ __device__ __forceinline__ void emit_candidate(bool pred, uint32_t spectrum, uin
     }
 }
 
+// Per-wave candidate staging in LDS: records are appended to the wave's own
+// slice (ballot + rank) and copied out with one global atomic per flush, so
+// the shared counter sees one atomic per slice-full instead of one per wave
+// step.  LDS writes and reads of a slice are by the same wave, ordered by the
+// wave barrier in the flush.
+struct Stage {
+    hs_candidate *buf;    // this wave's LDS slice
+    int count;            // records held (wave-uniform)
+};
+
+__device__ __forceinline__ void stage_flush(Stage &st, hs_candidate *cand, int64_t cap, unsigned long long *count) {
+    if (st.count == 0) return;
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    unsigned long long cb = 0;
+    if (lane == 0) cb = atomicAdd(count, (unsigned long long)st.count);
+    cb = __shfl(cb, 0);
+    for (int i = lane; i < st.count; i += 64)
+        if ((int64_t)(cb + i) < cap) cand[cb + i] = st.buf[i];
+    __builtin_amdgcn_wave_barrier();
+    st.count = 0;
+}
+
+template <int SLICE>
+__device__ __forceinline__ void stage_push(Stage &st, hs_candidate *cand, int64_t cap, unsigned long long *count,
+                                           bool pred, const hs_candidate &r) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const int cnt = __builtin_popcountll(mask);
+    if (st.count + cnt > SLICE) stage_flush(st, cand, cap, count);
+    const int lane = threadIdx.x & 63;
+    if (pred) st.buf[st.count + __builtin_popcountll(mask & ((1ull << lane) - 1ull))] = r;
+    st.count += cnt;
+}
+
 }  // namespace hs

@@ -90,13 +90,14 @@ struct XcdArgs {
 // is a ratio range [r0, r0 + delta) and holds the fundamentals (u, r) with
 // u r0 <= r < u (r0 + delta); its harmonics read row m = k u only at columns
 // [m r0, m (r0 + delta)], so the tile's window of rows u_lo..b is staged once.
-constexpr int kRayBudget = 8192;     // window elements staged per tile (default)
+constexpr int kRayLdsBytes = 42 * 1024;   // LDS of one tile's staged window (default; 3 tiles per CU)
 constexpr int kRayMaxBands = 512;    // bands of both sides (a band: tiles with the same top row b)
+constexpr int kRayMaxRows = 160;     // rows |z| of one side
 
 struct RayGeom {
     int64_t n_r;
     int32_t u_lo[2], u_hi[2];   // side 0: z = +u, side 1: z = -u; u_lo > u_hi: empty side
-    int32_t budget;             // window elements per tile
+    int32_t budget;             // window elements per tile (floats, or float pairs for greedy)
 };
 
 struct RayBand {
@@ -108,6 +109,20 @@ struct RayBand {
 };
 
 __host__ __device__ inline int64_t tri(int64_t x) { return x * (x + 1) / 2; }
+
+// Staged window: budget elements (a float, or a float pair for the greedy
+// sum), one pad element per 32, rounded to 16 bytes.
+__host__ __device__ inline size_t ray_window_bytes(int budget, bool greedy) {
+    const size_t n = (size_t)budget + ((size_t)budget >> 5) + 1;
+    return (n * (greedy ? 8 : 4) + 15) & ~(size_t)15;
+}
+
+// Largest budget whose window fits lds_bytes.
+inline int ray_budget_for(int lds_bytes, bool greedy) {
+    int e = lds_bytes / (greedy ? 8 : 4);
+    while (e > 0 && ray_window_bytes(e, greedy) > (size_t)lds_bytes) --e;
+    return e;
+}
 
 __host__ __device__ inline int ray_side_bands(const RayGeom &g, int side) {
     return g.u_lo[side] <= g.u_hi[side] ? g.u_hi[side] - g.u_lo[side] + 1 : 0;
@@ -139,6 +154,7 @@ __host__ __device__ inline bool ray_feasible(const RayGeom &g) {
         if (g.u_lo[side] > g.u_hi[side]) continue;
         const int64_t lo = g.u_lo[side], hi = g.u_hi[side];
         if (tri(hi) - tri(lo - 1) + (hi - lo + 1) > g.budget) return false;
+        if (hi - lo + 1 > kRayMaxRows) return false;
     }
     return ray_side_bands(g, 0) + ray_side_bands(g, 1) <= kRayMaxBands;
 }
@@ -185,7 +201,7 @@ struct hs_plan {
     int n_cu, n_xcd;             // device shape
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel
-    int ray_budget;              // window elements per tile of the ray-tiled plane kernel
+    int ray_lds;                 // LDS bytes of a tile's window in the ray-tiled plane kernel
     bool timing;                 // record stage events on every call
     std::vector<hipEvent_t> ev;  // 3 events per timed call: start, after norm, after sum
     int ev_used;                 // events of timed calls not yet read

@@ -62,120 +62,230 @@ __global__ __launch_bounds__(kRayMaxBands) void k_ray_bands(RayGeom g, RayBand *
     }
 }
 
+constexpr int kLoadBatch = 8;   // window loads in flight per thread
+
+// Constants of row u = |z| in a tile: harmonics inside the plane (kq), the
+// column threshold above which fewer fit, the window offsets of harmonic 1
+// and their first and second differences, the first column and the output
+// row offset.
+struct RowRec {
+    int32_t kq, kthr, T1, D1, E, rbase;
+    int64_t rowoff;
+};
+constexpr int kRayStage = 64;   // candidate records staged per wave
+
+// Window element: the stored power (simple sum) or the pair (x[c], x[c+1])
+// that a greedy step compares (one 8-byte LDS read per step).
+template <bool GREEDY>
+struct WinT {
+    using type = float;
+};
+template <>
+struct WinT<true> {
+    using type = float2;
+};
+
 template <int HMAX, bool GREEDY, bool F16>
 __global__ __launch_bounds__(kBlock) void k_sum_2d_ray(Ray2dArgs a) {
-    using L = Loader<F16>;
-    constexpr uint32_t eb = L::kBytes;
-    extern __shared__ float win[];
+    using W = typename WinT<GREEDY>::type;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    W *win = reinterpret_cast<W *>(lds_raw);
     __shared__ int64_t s_r0, s_r1;
     __shared__ int32_t s_side, s_b;
+    __shared__ float2 s_tab[HMAX];
+    __shared__ RowRec s_rows[kRayMaxRows];
 
     const uint32_t t = (blockIdx.x % (uint32_t)a.n_xcd) * a.per_xcd + blockIdx.x / (uint32_t)a.n_xcd;
     if (t >= a.n_tiles) return;   // uniform over the block
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = a.n_bands - 1;   // last band with first_tile <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.bands[mid].first_tile <= t) lo = mid;
-            else hi = mid - 1;
+    // the tile's band: the one band j with first_tile(j) <= t < first_tile(j + 1)
+    // (bands without tiles never match), found by all threads in parallel; the
+    // float table goes to LDS (one global read per entry per tile)
+    for (int j = threadIdx.x; j < a.n_bands; j += kBlock) {
+        const RayBand bd = a.bands[j];
+        if (bd.first_tile <= t && (j + 1 == a.n_bands || a.bands[j + 1].first_tile > t)) {
+            const int64_t r0 = bd.start + (int64_t)(t - bd.first_tile) * bd.delta;
+            s_r0 = r0;
+            s_r1 = r0 + bd.delta < bd.end ? r0 + bd.delta : bd.end;
+            s_side = bd.side;
+            s_b = bd.b;
         }
-        const RayBand bd = a.bands[lo];
-        const int64_t r0 = bd.start + (int64_t)(t - bd.first_tile) * bd.delta;
-        s_r0 = r0;
-        s_r1 = r0 + bd.delta < bd.end ? r0 + bd.delta : bd.end;
-        s_side = bd.side;
-        s_b = bd.b;
     }
+    if (threadIdx.x < HMAX) s_tab[threadIdx.x] = a.s.norm->t[threadIdx.x];
     __syncthreads();
-    const int64_t r0 = uni64(s_r0);
-    const int32_t dt = uni((int32_t)(s_r1 - r0));
+    const int32_t r0 = uni((int32_t)s_r0);            // b r0 <= n_r - 1 < 2^30
+    const int32_t dt = uni((int32_t)(s_r1 - s_r0));
     const int32_t side = uni(s_side), b = uni(s_b);
     const int32_t u_lo = a.g.u_lo[side], u_hi = a.g.u_hi[side];
     const int32_t sgn = side ? -1 : 1;
-    const int64_t n_r = a.s.n_r;
-    const int32_t c0 = (int32_t)tri(u_lo - 1);
+    const int32_t n_r = (int32_t)a.s.n_r;
+    const int32_t c0 = u_lo * (u_lo - 1) / 2;
+    const int lane = (int)(threadIdx.x & 63);
+    // logical window offset of row m (rows and offsets are small: 24-bit products)
+    auto row_base = [&](int32_t m) -> int32_t {
+        return __umul24((uint32_t)dt, (uint32_t)((__umul24((uint32_t)m, (uint32_t)(m - 1)) >> 1) - c0)) + (m - u_lo);
+    };
 
-    // 1. window rows u_lo..b, one wave per row at a time
+    // per-row constants of the fundamentals' walk (rows u_lo..b)
+    for (int32_t i = threadIdx.x; i <= b - u_lo; i += kBlock) {
+        const int32_t u = u_lo + i;
+        RowRec rr;
+        rr.kq = u_hi / u < a.s.H ? u_hi / u : a.s.H;   // harmonics inside the plane
+        rr.kthr = (n_r - 1) / rr.kq;                   // den > kthr <=> fewer than kq harmonics fit
+        rr.T1 = row_base(u);
+        rr.E = __umul24((uint32_t)dt, (uint32_t)(u * u));
+        rr.D1 = rr.E + __umul24((uint32_t)dt, (uint32_t)(u * (u - 1) / 2)) + u;
+        rr.rbase = u * r0;
+        rr.rowoff = ((int64_t)sgn * u - a.s.z_min) * (int64_t)n_r;
+        s_rows[i] = rr;
+    }
+
+    // 1. window: rows u_lo..b, row m = m dt + 1 logical columns from m r0
+    //    (loaded up to n_r - 1); each wave walks its rows u_lo + w, + 4, ...
+    //    in 64-column chunks and issues kLoadBatch chunks before storing
     {
-        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int32_t m = u_lo + w; m <= b; m += kBlock / 64) {
-            const int64_t col0 = (int64_t)m * r0;
-            if (col0 > n_r - 1) continue;
-            int64_t col1 = (int64_t)m * (r0 + dt);
-            if (col1 > n_r - 1) col1 = n_r - 1;
-            const int32_t len = (int32_t)(col1 - col0 + 1);
-            const int64_t row = (int64_t)sgn * m - a.s.z_min;
-            const __amdgpu_buffer_rsrc_t rs =
-                make_rsrc((const char *)a.s.plane + row * a.s.stride * eb, (uint32_t)(n_r * eb));
-            const int32_t base = dt * ((int32_t)tri(m - 1) - c0) + (m - u_lo);
-            for (int32_t c = lane; c < len; c += 64) win[lds_pos(base + c)] = L::one(rs, (uint32_t)(col0 + c));
+        int32_t m = u_lo + (int32_t)(threadIdx.x >> 6), c = 0;   // wave-uniform cursor
+        while (m <= b) {
+            W v[kLoadBatch];
+            int32_t pos[kLoadBatch];
+#pragma unroll
+            for (int j = 0; j < kLoadBatch; ++j) {
+                pos[j] = -1;
+                if (m <= b) {
+                    const int32_t col0 = m * r0;               // <= n_r - 1 for m <= b
+                    const int32_t avail = n_r - col0;          // columns left in the row
+                    const int32_t col = c + lane;
+                    if (col <= m * dt && col < avail) {
+                        const char *row = (const char *)a.s.plane +
+                                          ((int64_t)sgn * m - a.s.z_min) * a.s.stride * (int64_t)(F16 ? 2 : 4);
+                        float x0, x1 = 0.0f;
+                        if constexpr (F16) {
+                            const uint16_t *h = (const uint16_t *)row + col0 + col;
+                            x0 = (float)__builtin_bit_cast(_Float16, h[0]);
+                            if (GREEDY && col + 1 < avail) x1 = (float)__builtin_bit_cast(_Float16, h[1]);
+                        } else {
+                            const float *f = (const float *)row + col0 + col;
+                            x0 = f[0];
+                            if (GREEDY && col + 1 < avail) x1 = f[1];
+                        }
+                        if constexpr (GREEDY)
+                            v[j] = make_float2(x0, x1);
+                        else
+                            v[j] = x0;
+                        pos[j] = lds_pos(row_base(m) + col);
+                    }
+                    c += 64;
+                    if (c > m * dt) {
+                        m += kBlock / 64;
+                        c = 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kLoadBatch; ++j)
+                if (pos[j] >= 0) win[pos[j]] = v[j];
         }
     }
     __syncthreads();
 
-    // 2. fundamentals of rows u_lo..b, consecutive lanes on consecutive columns
-    const NormRec *nr = a.s.norm;
-    const int valid = nr->valid;
-    const float2 *tab = nr->t;
-    const int64_t n_end = a.s.n_end < n_r ? a.s.n_end : n_r;
-    const int32_t nf = dt * ((int32_t)tri(b) - c0);
-    for (int32_t f0 = 0; f0 < nf; f0 += kBlock) {
-        const int32_t f = f0 + (int32_t)threadIdx.x;
-        int32_t u = u_lo, R = 0;
-        if (f < nf) {
-            const int32_t y = f / dt + c0;   // row u: the smallest with tri(u) > y
-            u = (int32_t)((__builtin_sqrtf(8.0f * (float)y + 1.0f) - 1.0f) * 0.5f) + 1;
-            while (tri(u) <= y) ++u;
-            while (tri(u - 1) > y) --u;
-            R = f - dt * ((int32_t)tri(u - 1) - c0);
-        }
-        const int64_t r = (int64_t)u * r0 + R;
-        const bool in = f < nf && r < n_r;
+    // 2. fundamentals, flat order (row u_lo first, columns within a row):
+    //    wave w owns a contiguous quarter, lane l takes positions l, l + 64,
+    //    ... of it, so each lane's (row u, column offset R) advances by 64
+    //    per iteration and rows are crossed incrementally.  Per row the lane
+    //    keeps the window offset of harmonic k's row, T_k = base(k u), as a
+    //    second-order difference (T_{k+1} = T_k + D_k, D_{k+1} = D_k + dt u^2).
+    //    Candidates are staged per wave behind the window.
+    Stage st{(hs_candidate *)(lds_raw + ray_window_bytes(a.g.budget, GREEDY)) + (threadIdx.x >> 6) * kRayStage, 0};
+    const int valid = a.s.norm->valid;
+    const int32_t n_end = a.s.n_end < (int64_t)n_r ? (int32_t)a.s.n_end : n_r;
+    const int32_t nr1 = n_r - 1;
+    const int32_t nf = __umul24((uint32_t)dt, (uint32_t)(b * (b + 1) / 2 - c0));
+    const int32_t wq = (nf + kBlock - 1) / kBlock * 64;   // per wave: ceil(nf / 4) rounded up to 64
+    const int32_t fw0 = (int32_t)(threadIdx.x >> 6) * wq;
+    const int32_t fw1 = fw0 + wq < nf ? fw0 + wq : nf;
+    int32_t u = u_lo, R = 0;
+    if (fw0 + lane < nf) {
+        // row of flat position f: the smallest u with tri(u) > f / dt + c0
+        const int32_t f = fw0 + lane;
+        const int32_t y = (int32_t)((float)f / (float)dt) + c0;   // exact: f, dt < 2^24
+        u = (int32_t)((__builtin_sqrtf(8.0f * (float)y + 1.0f) - 1.0f) * 0.5f) + 1;
+        while (u * (u + 1) / 2 <= y) ++u;
+        while (u * (u - 1) / 2 > y) --u;
+        R = f - __umul24((uint32_t)dt, (uint32_t)(u * (u - 1) / 2 - c0));
+    }
+    // per-row state of the lane
+    int32_t rowlen = u * dt;
+    RowRec rw = s_rows[u - u_lo];
+    for (int32_t f0 = fw0; f0 < fw1; f0 += 64) {   // wave-uniform trip count
+        const int32_t r = rw.rbase + R;
+        const bool in = f0 + lane < fw1 && r < n_r;
         int K = 0;
         if (in && valid && r >= a.s.first_bin && r < n_end) {
-            const uint32_t kk = (uint32_t)(n_r - 1) / (uint32_t)(GREEDY ? r + 1 : r);   // n_r < 2^30
-            const int kz = u_hi / u;
-            K = (int)kk < kz ? (int)kk : kz;
-            if (K > a.s.H) K = a.s.H;
+            const int32_t den = GREEDY ? r + 1 : r;
+            K = rw.kq;
+            if (den > rw.kthr) {   // exact quotient (< kq <= 32) from a float estimate
+                int q = (int)((float)nr1 / (float)den);
+                if ((int64_t)(q + 1) * den <= nr1) ++q;
+                else if ((int64_t)q * den > nr1) --q;
+                K = q;
+            }
         }
-        float S = 0.0f, best = 0.0f;
+        float S = 0.0f, best = -__builtin_inff();   // any finite SNR beats it: the first eligible k wins
         int kb = 0, db = 0;
-        int32_t d = 0;
+        int32_t d = 0, T = rw.T1, D = rw.D1, kR = R;
 #pragma unroll
         for (int k = 1; k <= HMAX; ++k) {
             if (k > K) break;
-            const int32_t m = k * u;
-            const int32_t g = dt * ((int32_t)tri(m - 1) - c0) + (m - u_lo) + k * R + d;
+            const int32_t g = T + kR + d;
             float v;
             if constexpr (GREEDY) {
-                const float x0 = win[lds_pos(g)], x1 = win[lds_pos(g + 1)];
-                const bool up = x1 > x0;
-                v = up ? x1 : x0;
+                const float2 p = win[lds_pos(g)];
+                const bool up = p.y > p.x;
+                v = up ? p.y : p.x;
                 d += up ? 1 : 0;
             } else {
                 v = win[lds_pos(g)];
             }
             S = S + v;
-            const float2 tk = tab[k - 1];
+            const float2 tk = s_tab[k - 1];
             const float snr = __builtin_fmaf(S, tk.x, tk.y);
             if ((a.s.kmask >> (k - 1)) & 1ull) {
-                if (kb == 0 || snr > best) {
+                if (snr > best) {
                     best = snr;
                     kb = k;
                     db = d;
                 }
             }
+            T += D;
+            D += rw.E;
+            kR += R;
         }
         const Best bs{kb ? best : 0.0f, kb, db};
-        const int64_t o = ((int64_t)sgn * u - a.s.z_min) * n_r + r;
+        const int64_t o = rw.rowoff + r;
         if (in) {
             if (a.s.snr) a.s.snr[o] = bs.snr;
             if (a.s.harm) a.s.harm[o] = (uint8_t)bs.harm;
             if (a.s.drift) a.s.drift[o] = (uint8_t)bs.drift;
         }
-        if (a.s.cand)
-            emit_candidate(in && bs.harm > 0 && bs.snr > a.s.thr, 0u, (uint32_t)o, bs, a.s.cand, a.s.cap, a.s.count);
+        if (a.s.cand) {
+            hs_candidate rec;
+            rec.spectrum = 0u;
+            rec.bin = (uint32_t)o;
+            rec.snr = bs.snr;
+            rec.harm = (uint16_t)bs.harm;
+            rec.drift = (uint16_t)bs.drift;
+            stage_push<kRayStage>(st, a.s.cand, a.s.cap, a.s.count, in && bs.harm > 0 && bs.snr > a.s.thr, rec);
+        }
+        R += 64;
+        if (R >= rowlen && u < b) {
+            do {
+                R -= rowlen;
+                ++u;
+                rowlen += dt;
+            } while (R >= rowlen && u < b);
+            rw = s_rows[u - u_lo];
+        }
     }
+    if (a.s.cand) stage_flush(st, a.s.cand, a.s.cap, a.s.count);
 }
 
 template <int HMAX>
@@ -215,7 +325,8 @@ hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, hipSt
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(a.per_xcd * (uint32_t)a.n_xcd);
-    const size_t lds = sizeof(float) * ((size_t)a.g.budget + ((size_t)a.g.budget >> 5) + 1);
+    const size_t lds = ray_window_bytes(a.g.budget, greedy) +
+                       (a.s.cand ? sizeof(hs_candidate) * (kBlock / 64) * kRayStage : 0);
     switch (hmax) {
         case 4: return ray_h<4>(a, greedy, f16, grid, lds, st);
         case 8: return ray_h<8>(a, greedy, f16, grid, lds, st);

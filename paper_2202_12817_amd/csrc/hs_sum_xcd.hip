@@ -79,41 +79,11 @@ __device__ __forceinline__ int keff(int64_t n, int64_t len, int64_t first_bin, i
     return kk < (uint32_t)H ? (int)kk : H;
 }
 
-// Candidate staging: each wave collects its records in its own LDS slice and
-// reserves space in the global list with one atomic per kStage records (a
-// device-wide atomic per record would serialise the whole kernel on one
-// address).  Wave-private, so no barrier is needed; the wave's LDS accesses are
-// ordered by the wave barrier below.
+// Candidate staging (Stage in hs_device.h): each wave collects its records in
+// its own LDS slice of kStage records and reserves space in the global list
+// with one atomic per flush (a device-wide atomic per record would serialise
+// the whole kernel on one address).
 constexpr int kStage = 256;
-
-struct Stage {
-    hs_candidate *buf;    // this wave's LDS slice [kStage]
-    int count;            // records held (wave-uniform)
-};
-
-__device__ __forceinline__ void stage_flush(Stage &st, const SumArgs &a) {
-    if (st.count == 0) return;
-    const int lane = threadIdx.x & 63;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    unsigned long long cb = 0;
-    if (lane == 0) cb = atomicAdd(a.count, (unsigned long long)st.count);
-    cb = __shfl(cb, 0);
-    for (int i = lane; i < st.count; i += 64)
-        if ((int64_t)(cb + i) < a.cap) a.cand[cb + i] = st.buf[i];
-    __builtin_amdgcn_wave_barrier();
-    st.count = 0;
-}
-
-__device__ __forceinline__ void stage_push(Stage &st, const SumArgs &a, bool pred, const hs_candidate &r) {
-    const uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    const int cnt = __builtin_popcountll(mask);
-    if (st.count + cnt > kStage) stage_flush(st, a);
-    const int lane = threadIdx.x & 63;
-    if (pred) st.buf[st.count + __builtin_popcountll(mask & ((1ull << lane) - 1ull))] = r;
-    st.count += cnt;
-}
 
 // One pass: kBlock * F consecutive fundamentals starting at p0 (lane owns
 // p0 + f kBlock + threadIdx.x), restricted to [p0, p_end).
@@ -210,7 +180,7 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
             r.snr = bs;
             r.harm = (uint16_t)kb[f];
             r.drift = (uint16_t)db[f];
-            stage_push(st, a, in && kb[f] > 0 && bs > a.thr, r);
+            stage_push<kStage>(st, a.cand, a.cap, a.count, in && kb[f] > 0 && bs > a.thr, r);
         }
     }
 }
@@ -317,7 +287,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) 
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_ticket);
     }
-    if (a.cand) stage_flush(st, a);
+    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
 }
 
 template <int HMAX, bool GREEDY, bool F16>

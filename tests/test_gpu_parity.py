@@ -290,7 +290,7 @@ def test_2d_dense(dev, mode, shape):
                                    (-2, 30, 12007), (-126, 126, 700), (-130, 130, 300), (-1, 1, 65537)])
 @pytest.mark.parametrize("opts", [{}, {"first_bin": 5, "fundamental_end": 1700, "harmonic_mask": 0b1010101010}])
 def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
-    """The ray-tiled plane kernel (default) against the one-thread-per-fundamental kernel,
+    """The ray-tiled plane kernel against the one-thread-per-fundamental kernel,
     bit for bit, and against the oracle; z ranges of one side, both sides, beyond the
     tile budget (the default falls back to the plain kernel) and a ragged last tile."""
     z_min, z_max, n_r = shape
@@ -298,7 +298,8 @@ def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
     pt = torch.from_numpy(p).to(dev)
     H = 16
     print("2d ray", mode, shape, opts, flush=True)
-    got = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size, **opts)
+    got = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size,
+                        kernel="persistent", **opts)
     ref = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size,
                         kernel="plain", **opts)
     for k in ("harm", "drift"):
@@ -312,14 +313,15 @@ def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
         check_dense(got, w, None, "2d ray %s %s" % (mode, shape))
 
 
+@pytest.mark.parametrize("kernel", ["auto", "persistent"])
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
-def test_2d_fp16_storage(dev, mode):
+def test_2d_fp16_storage(dev, mode, kernel):
     z_min, z_max, n_r = -9, 9, 30011
     p = _plane(z_max - z_min + 1, n_r, 77)
     q = oracle.quantize_f16(p.reshape(-1), np.float32(1.0)).reshape(p.shape)
     dec = q.astype(np.float32)
     pt = torch.from_numpy(q.view(np.int16)).to(dev).view(torch.float16)
-    got = _ops().sum_2d(pt, z_min, z_max, 16, mode, with_norm=True)
+    got = _ops().sum_2d(pt, z_min, z_max, 16, mode, with_norm=True, kernel=kernel)
     check_dense(got, oracle.hs_2d(dec, z_min, z_max, 16, MODES[mode]),
                 oracle.hs_2d(dec, z_min, z_max, 16, MODES[mode], precision="f64"), "2d fp16 " + mode)
     check_norm(got, dec, 1, 16, "2d fp16")
