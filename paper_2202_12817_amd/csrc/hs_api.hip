@@ -269,14 +269,15 @@ hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_str
     g.u_hi[0] = z_max;
     g.u_lo[1] = -z_max > 1 ? -z_max : 1;
     g.u_hi[1] = -z_min;
-    g.budget = hs::ray_budget_for(p->ray_lds, greedy);
+    g.budget = hs::ray_budget_for(p->ray_lds, false);
+    if (g.budget > hs::kBlock * hs::kRayMaxPer) g.budget = hs::kBlock * hs::kRayMaxPer;
     if (p->desc.kernel == HS_KERNEL_PERSISTENT && hs::ray_feasible(g)) {
         hs::Ray2dArgs ra{};
         ra.s = a;
         ra.g = g;
         ra.bands = p->ray;
         ra.n_xcd = p->n_xcd;
-        e = hs::launch_sum_2d_ray(ra, p->hmax, greedy, f16, st);
+        e = hs::launch_sum_2d_ray(ra, p->hmax, greedy, f16, p->n_cu, st);
         if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel (ray tiles)");
         if (z_min <= 0 && z_max >= 0) {   // row z = 0
             a.row0 = -z_min;

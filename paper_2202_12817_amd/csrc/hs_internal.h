@@ -90,14 +90,15 @@ struct XcdArgs {
 // is a ratio range [r0, r0 + delta) and holds the fundamentals (u, r) with
 // u r0 <= r < u (r0 + delta); its harmonics read row m = k u only at columns
 // [m r0, m (r0 + delta)], so the tile's window of rows u_lo..b is staged once.
-constexpr int kRayLdsBytes = 42 * 1024;   // LDS of one tile's staged window (default; 3 tiles per CU)
+constexpr int kRayLdsBytes = 22 * 1024;   // LDS of one tile's staged window (default; 5 workgroups per CU)
+constexpr int kRayMaxPer = 24;            // window elements per thread: budget <= 256 kRayMaxPer
 constexpr int kRayMaxBands = 512;    // bands of both sides (a band: tiles with the same top row b)
 constexpr int kRayMaxRows = 160;     // rows |z| of one side
 
 struct RayGeom {
     int64_t n_r;
     int32_t u_lo[2], u_hi[2];   // side 0: z = +u, side 1: z = -u; u_lo > u_hi: empty side
-    int32_t budget;             // window elements per tile (floats, or float pairs for greedy)
+    int32_t budget;             // window elements (floats) per tile, <= 256 kRayMaxPer
 };
 
 struct RayBand {
@@ -110,8 +111,8 @@ struct RayBand {
 
 __host__ __device__ inline int64_t tri(int64_t x) { return x * (x + 1) / 2; }
 
-// Staged window: budget elements (a float, or a float pair for the greedy
-// sum), one pad element per 32, rounded to 16 bytes.
+// Staged window: budget elements (floats, or float pairs), one pad element
+// per 32, rounded to 16 bytes.
 __host__ __device__ inline size_t ray_window_bytes(int budget, bool greedy) {
     const size_t n = (size_t)budget + ((size_t)budget >> 5) + 1;
     return (n * (greedy ? 8 : 4) + 15) & ~(size_t)15;
@@ -165,8 +166,7 @@ struct Ray2dArgs {
     RayBand *bands;             // [n_bands], written by the band kernel of the same launch sequence
     int32_t n_bands;
     uint32_t n_tiles;
-    int32_t n_xcd;              // tile ranges: XCD q owns tiles [q per_xcd, (q + 1) per_xcd)
-    uint32_t per_xcd;
+    int32_t n_xcd;              // XCD q owns tiles [n_tiles q / n_xcd, n_tiles (q + 1) / n_xcd)
 };
 
 hipError_t launch_stats(const StatsArgs &a, int groups, bool f16, hipStream_t st);
@@ -180,7 +180,7 @@ hipError_t launch_sum_xcd(const XcdArgs &a, int hmax, bool greedy, bool f16, int
 hipError_t launch_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out, hipStream_t st);
 hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3 grid, hipStream_t st);
 hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st);
-hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, hipStream_t st);
+hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, int n_cu, hipStream_t st);
 
 }  // namespace hs
 
