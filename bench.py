@@ -323,6 +323,10 @@ def main():
             hs.hs_quantize_f16(base + 4 * int(off[s]), int(lengths[s]), scale, x16.data_ptr() + 2 * int(off[s]),
                                stream)
         plan16 = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F16, max_spectra=B, threshold=THRESHOLD)
+        if not args.launch:
+            hs.hs_plan_tune_batched(plan16.handle, x16, ot, B, None, None, None, None, cand, cap, count,
+                                    args.tune_cache, stream)
+        shape16 = hs.hs_plan_get_launch(plan16.handle)
         for _ in range(args.warmup):
             step(plan16, x16)
         torch.cuda.synchronize()
@@ -339,6 +343,7 @@ def main():
                                   "speedup_vs_plain_fp32": plain_s / e16,
                                   "hbm_gbs_compulsory": (2 * n_bins + 16 * n_cand16) / e16 / 1e9,
                                   "stage_ms": {"normalisation": n16 / max(1, c16), "harmonic_sum": s16 / max(1, c16)},
+                                  "launch": {"fundamentals_per_lane": shape16[0], "workgroups_per_cu": shape16[1]},
                                   "candidates": n_cand16}
         del x16
 

@@ -181,7 +181,8 @@ def test_fp16_storage_sums(dev, mode):
 @pytest.mark.parametrize("kernel", ["persistent", "plain"])
 @pytest.mark.parametrize("mode", ["standard", "greedy"])
 @pytest.mark.parametrize("f16", [False, True])
-def test_batched_small(dev, mode, f16, kernel):
+@pytest.mark.parametrize("H", [13, 32])
+def test_batched_small(dev, mode, f16, kernel, H):
     B = 37
     x, off = synthetic.config3(n_spectra=B, lo=2, hi=90000, seed=61)
     thr = 4.0
@@ -191,15 +192,15 @@ def test_batched_small(dev, mode, f16, kernel):
     else:
         xt = torch.from_numpy(x).to(dev)
     ot = torch.from_numpy(off).to(dev)
-    print("batched", mode, f16, flush=True)
-    got = _ops().sum_batched(xt, ot, 32, mode, thr, dense=True, candidates=True, capacity=x.size,
+    print("batched", mode, f16, kernel, H, flush=True)
+    got = _ops().sum_batched(xt, ot, H, mode, thr, dense=True, candidates=True, capacity=x.size,
                              with_norm=True, kernel=kernel)
-    w = oracle.hs_batched(x, off, 32, MODES[mode], thr, dense=True)
+    w = oracle.hs_batched(x, off, H, MODES[mode], thr, dense=True)
     ms = _np(got["mu_sigma"])
     for s in range(B):
         sl = slice(off[s], off[s + 1])
         w32 = w["spectra"][s]
-        w64 = oracle.hs_1d(x[sl], 32, MODES[mode], precision="f64")
+        w64 = oracle.hs_1d(x[sl], H, MODES[mode], precision="f64")
         check_dense({k: got[k][sl] for k in ("snr", "harm", "drift")}, w32, w64, "spectrum %d" % s)
         if off[s + 1] - off[s] > 1:
             assert (ms[s, 0], ms[s, 1]) == (w32["mu1"], w32["sigma1"]) or not np.isfinite(w32["sigma1"])
@@ -289,15 +290,15 @@ def test_2d_dense(dev, mode, shape):
 @pytest.mark.parametrize("shape", [(-20, 20, 20011), (-100, 100, 3001), (3, 11, 9000), (-13, -1, 7001),
                                    (-2, 30, 12007), (-126, 126, 700), (-130, 130, 300), (-1, 1, 65537)])
 @pytest.mark.parametrize("opts", [{}, {"first_bin": 5, "fundamental_end": 1700, "harmonic_mask": 0b1010101010}])
-def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
+@pytest.mark.parametrize("H", [5, 16, 32])
+def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts, H):
     """The ray-tiled plane kernel against the one-thread-per-fundamental kernel,
     bit for bit, and against the oracle; z ranges of one side, both sides, beyond the
     tile budget (the default falls back to the plain kernel) and a ragged last tile."""
     z_min, z_max, n_r = shape
     p = _plane(z_max - z_min + 1, n_r, n_r + 3)
     pt = torch.from_numpy(p).to(dev)
-    H = 16
-    print("2d ray", mode, shape, opts, flush=True)
+    print("2d ray", mode, shape, opts, H, flush=True)
     got = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size,
                         kernel="persistent", **opts)
     ref = _ops().sum_2d(pt, z_min, z_max, H, mode, candidates=True, threshold=3.5, capacity=p.size,
@@ -308,7 +309,7 @@ def test_2d_ray_tiles_equal_plain_kernel(dev, mode, shape, opts):
     ra, na = _cands(got)
     rb, nb = _cands(ref)
     assert na == nb and _same_records(ra, rb)
-    if p.size <= 2_000_000:
+    if p.size <= 2_000_000 and H != 5:
         w = oracle.hs_2d(p, z_min, z_max, H, MODES[mode], **opts)
         check_dense(got, w, None, "2d ray %s %s" % (mode, shape))
 
