@@ -264,6 +264,55 @@ def test_config3_full_size_sampled(dev):
     del xt
 
 
+def test_batched_max_spectra(dev):
+    """The most spectra one call accepts (65535), lengths 2..40 (length 2: no
+    fundamental sums a harmonic beyond the fundamental step), greedy H = 32:
+    sampled spectra checked against the oracle, dense and candidates."""
+    B = 65535
+    g = np.random.default_rng(92)
+    lengths = g.integers(2, 41, size=B)
+    off = np.zeros(B + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lengths)
+    x = synthetic.exp_noise(int(off[-1]), 92)
+    xt, ot = torch.from_numpy(x).to(dev), torch.from_numpy(off).to(dev)
+    got = _ops().sum_batched(xt, ot, 32, "greedy", 3.0, dense=True, candidates=True, capacity=x.size,
+                             with_norm=True)
+    sample = np.unique(np.concatenate([np.arange(50), np.arange(B - 50, B), g.choice(B, 1500, replace=False)]))
+    w = oracle.hs_batched(x, off, 32, oracle.GREEDY, 3.0, dense=True, spectra=sample)
+    ms = _np(got["mu_sigma"])
+    for s in sample:
+        sl = slice(off[s], off[s + 1])
+        w32 = w["spectra"][s]
+        check_dense({k: got[k][sl] for k in ("snr", "harm", "drift")}, w32, None, "spectrum %d" % s)
+        assert (ms[s, 0], ms[s, 1]) == (w32["mu1"], w32["sigma1"]) or not np.isfinite(w32["sigma1"])
+    recs, n = _cands(got)
+    keep = np.isin(recs["spectrum"], sample)
+    assert _same_records(recs[keep], w["candidates"])
+
+
+@pytest.mark.slow
+def test_1d_max_length(dev):
+    """The longest spectrum a call accepts, 2^30 - 1 FP32 bins (4 GiB), greedy
+    H = 32, persistent kernel: exact statistics and tables, and sampled
+    fundamentals (both ends, every harmonic-count boundary, random bins)."""
+    n = (1 << 30) - 1
+    x = synthetic.exp_noise(n, 93)
+    print("1d max length: statistics", flush=True)
+    mu1, sigma1 = oracle.norm_from_data(x, 1)
+    xt = torch.from_numpy(x).to(dev)
+    got = _ops().sum_1d(xt, 32, "greedy", with_norm=True)
+    ms = _np(got["mu_sigma"])[0]
+    assert (ms[0], ms[1]) == (mu1, sigma1)
+    g = np.random.default_rng(93)
+    edges = [(n - 1) // (k + 1) - 1 for k in range(1, 33)]   # greedy K changes after these bins
+    idx = np.unique(np.concatenate([np.arange(0, 3000), np.arange(n - 3000, n), g.integers(0, n, 20000),
+                                    np.array([e + dlt for e in edges for dlt in (-2, -1, 0, 1, 2)])]))
+    idx = idx[(idx >= 0) & (idx < n)]
+    w = oracle.hs_1d(x, 32, oracle.GREEDY, norm=(mu1, sigma1), idx=idx)
+    it = torch.from_numpy(idx).to(dev)
+    check_dense({k: got[k][it] for k in ("snr", "harm", "drift")}, w, None, "1d max length")
+
+
 # ---------------------------------------------------------------------------
 # 2D
 # ---------------------------------------------------------------------------
@@ -339,6 +388,17 @@ def test_2d_strided_rows_and_candidates(dev):
     recs, n = _cands(got)
     wc = oracle.candidates(w["snr"].reshape(-1), w["harm"].reshape(-1), w["drift"].reshape(-1), 3.0)
     assert n == wc.size and _same_records(recs, wc)
+
+
+def test_2d_max_rows(dev):
+    """The most rows a plane may have (65535, z = -32767..32767), 48 columns,
+    greedy H = 16: every row's harmonic rows k z stay inside the plane only
+    for small |z|, the truncation rule is exercised on every row."""
+    z_min, z_max, n_r = -32767, 32767, 48
+    p = _plane(z_max - z_min + 1, n_r, 94)
+    got = _ops().sum_2d(torch.from_numpy(p).to(dev), z_min, z_max, 16, "greedy", with_norm=True)
+    check_dense(got, oracle.hs_2d(p, z_min, z_max, 16, oracle.GREEDY), None, "2d max rows")
+    check_norm(got, p, 1, 16, "2d max rows")
 
 
 @pytest.mark.slow
