@@ -110,6 +110,20 @@ def keff_sum(lengths, H, greedy, first_bin=1):
     return total
 
 
+def line_bytes_sum(lengths, H, greedy, elem, first_bin=1):
+    """Bytes moved from L2 to the CUs at cache-line granularity (128 B lines,
+    waves of 64 consecutive fundamentals): a fundamental-step at harmonic k
+    moves about min(k elem, 128) bytes, summed over every step."""
+    total = 0
+    for N in lengths:
+        N = int(N)
+        for k in range(1, H + 1):
+            hi = (N - 1) // k - (1 if greedy else 0)
+            if hi >= first_bin:
+                total += (min(hi, N - 1) - first_bin + 1) * min(k * elem, 128)
+    return total
+
+
 def keff_sum_2d(n_r, z_min, z_max, H, greedy, first_bin=1):
     """Sum of K_eff over the f-fdot plane (row z truncates at the first harmonic row outside the plane)."""
     total = 0
@@ -247,6 +261,7 @@ def main():
     value = work * args.steps / elapsed
 
     in_bytes = 4 * n_bins
+    lines = line_bytes_sum(lengths, H, True, 4)
     cand_bytes = 16 * min(n_cand, cap)
     sum_avg_ms = sum_ms / max(1, calls)
     norm_avg_ms = norm_ms / max(1, calls)
@@ -277,6 +292,10 @@ def main():
         "launch": {"fundamentals_per_lane": shape[0], "workgroups_per_cu": shape[1], "tuned": not args.launch},
         "graph_replay": {"ms_per_step": graph_ms, "value": work / (graph_ms * 1e-3),
                          "graphs_recorded": graph_info[0], "replays": graph_info[1]},
+        "gather": {"touched_bytes": 8 * work, "touched_gbs": 8 * work / (sum_avg_ms * 1e-3) / 1e9,
+                   "l2_to_cu_bytes": lines, "l2_to_cu_tbs": lines / (sum_avg_ms * 1e-3) / 1e12,
+                   "note": "harmonic-sum kernel: 8 B touched per greedy step (the compared pair); "
+                           "min(4 k, 128) B per step at cache-line granularity"},
         "roofline": {"bound": "hbm", "kernel": SUM_KERNEL % shape[0], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": read_traffic(SUM_KERNEL % shape[0])},

@@ -110,10 +110,29 @@ void hs_plan_desc_init(hs_plan_desc *desc);
 
 /*
  * Validate *desc and create a plan on the current HIP device, allocating its
- * workspace (statistics and tables for max_spectra spectra).  *plan is set on
- * success and must be released with hs_plan_destroy.
+ * device workspace (one hipMalloc of hs_plan_workspace_bytes: statistics and
+ * tables for max_spectra spectra).  *plan is set on success and must be
+ * released with hs_plan_destroy.
  */
 hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan);
+
+/*
+ * Device workspace of a plan with this descriptor, in bytes (host-only
+ * arithmetic; validates *desc like hs_plan_create).  It grows with
+ * max_spectra: statistics partials, normalisation records and work-queue
+ * counters of every spectrum of a call.
+ */
+hs_status hs_plan_workspace_bytes(const hs_plan_desc *desc, size_t *bytes);
+
+/*
+ * Like hs_plan_create, but the plan keeps its device workspace in the
+ * caller's buffer: workspace is device memory on the current device, 256-byte
+ * aligned, at least hs_plan_workspace_bytes bytes, owned by the caller and
+ * kept alive (and not used for anything else) until hs_plan_destroy.  The
+ * plan then allocates no device memory.  HS_ERR_ARG for a NULL, misaligned or
+ * too small buffer.
+ */
+hs_status hs_plan_create_in(const hs_plan_desc *desc, void *workspace, size_t bytes, hs_plan **plan);
 
 /* Release the plan (waits for nothing: the caller ensures no call is in flight). */
 hs_status hs_plan_destroy(hs_plan *plan);

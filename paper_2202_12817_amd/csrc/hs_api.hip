@@ -537,6 +537,102 @@ hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_
     return HS_OK;
 }
 
+hs_status check_desc(const hs_plan_desc &d) {
+    if (d.harmonics < 1) return fail(HS_ERR_ARG, "harmonics must be >= 1");
+    if (d.harmonics > HS_MAX_HARMONICS) return fail(HS_ERR_UNSUPPORTED, "harmonics above 32 not supported");
+    if (d.mode != HS_STANDARD && d.mode != HS_GREEDY) return fail(HS_ERR_ARG, "bad mode");
+    if (d.dtype != HS_F32 && d.dtype != HS_F16) return fail(HS_ERR_ARG, "bad dtype");
+    if (d.first_bin < 1) return fail(HS_ERR_ARG, "first_bin must be >= 1");
+    if (d.fundamental_end < 0) return fail(HS_ERR_ARG, "fundamental_end must be >= 0");
+    if (d.max_spectra < 1 || d.max_spectra > 65535) return fail(HS_ERR_ARG, "max_spectra out of range [1, 65535]");
+    if (d.harmonics < 64 && (d.report_mask >> d.harmonics) != 0) return fail(HS_ERR_ARG, "report_mask above H");
+    if (d.harmonic_mask != 0 && eligible_mask(d) == 0) return fail(HS_ERR_ARG, "harmonic_mask selects no k <= H");
+    if (!(d.threshold == d.threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
+    if (d.kernel < HS_KERNEL_AUTO || d.kernel > HS_KERNEL_PLAIN) return fail(HS_ERR_ARG, "bad kernel choice");
+    return HS_OK;
+}
+
+// Device workspace of a plan: one block, pieces at 256-byte aligned offsets.
+struct Layout {
+    int parts_cap;
+    size_t norm, parts, tickets, prefix, ray, total;
+};
+
+constexpr size_t kWsAlign = 256;
+
+size_t align_up(size_t v) { return (v + kWsAlign - 1) & ~(kWsAlign - 1); }
+
+Layout layout(const hs_plan_desc &d) {
+    Layout l{};
+    int64_t parts = (int64_t)d.max_spectra * hs::kChunksBatched;
+    if (parts < hs::kChunks2D) parts = hs::kChunks2D;
+    if (parts < hs::kChunks1D) parts = hs::kChunks1D;
+    l.parts_cap = (int)parts;
+    size_t o = 0;
+    l.norm = o;
+    o = align_up(o + sizeof(hs::NormRec) * (size_t)d.max_spectra);
+    l.parts = o;
+    o = align_up(o + sizeof(hs::StatPart) * (size_t)l.parts_cap);
+    l.tickets = o;
+    o = align_up(o + sizeof(uint32_t) * hs::kMaxXcd);
+    l.prefix = o;
+    o = align_up(o + sizeof(uint32_t) * ((size_t)d.max_spectra + 1));
+    l.ray = o;
+    o = align_up(o + sizeof(hs::RayBand) * hs::kRayMaxBands);
+    l.total = o;
+    return l;
+}
+
+// Plan on the current device; workspace == NULL: the plan allocates (and
+// later frees) its workspace, else it uses the caller's.
+hs_status create_plan(const hs_plan_desc *desc, void *workspace, size_t bytes, hs_plan **plan) {
+    if (!desc || !plan) return fail(HS_ERR_ARG, "null argument");
+    *plan = nullptr;
+    const hs_plan_desc &d = *desc;
+    hs_status cs = check_desc(d);
+    if (cs != HS_OK) return cs;
+    const Layout l = layout(d);
+    if (workspace) {
+        if (((uintptr_t)workspace & (kWsAlign - 1)) != 0) return fail(HS_ERR_ARG, "workspace not 256-byte aligned");
+        if (bytes < l.total) return fail(HS_ERR_ARG, "workspace smaller than hs_plan_workspace_bytes");
+    }
+    hs_plan *p = new (std::nothrow) hs_plan();
+    if (!p) return fail(HS_ERR_NOMEM, "host allocation failed");
+    p->desc = d;
+    p->hmax = bucket(d.harmonics);
+    p->max_groups = d.max_spectra;
+    p->parts_cap = l.parts_cap;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+    if (workspace) {
+        p->ws = (char *)workspace;
+        p->ws_owned = false;
+    } else {
+        e = hipMalloc((void **)&p->ws, l.total);
+        if (e != hipSuccess) {
+            delete p;
+            (void)hipGetLastError();
+            return fail(HS_ERR_NOMEM, "device workspace allocation failed");
+        }
+        p->ws_owned = true;
+    }
+    p->norm = (hs::NormRec *)(p->ws + l.norm);
+    p->parts = (hs::StatPart *)(p->ws + l.parts);
+    p->tickets = (uint32_t *)(p->ws + l.tickets);
+    p->prefix = (uint32_t *)(p->ws + l.prefix);
+    p->ray = (hs::RayBand *)(p->ws + l.ray);
+    hs_status ss = setup_xcd(p);
+    if (ss != HS_OK) {
+        hs_plan_destroy(p);
+        return ss;
+    }
+    *plan = p;
+    return HS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -556,57 +652,21 @@ void hs_plan_desc_init(hs_plan_desc *d) {
     d->kernel = HS_KERNEL_AUTO;
 }
 
-hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
-    if (!desc || !plan) return fail(HS_ERR_ARG, "null argument");
-    *plan = nullptr;
-    const hs_plan_desc &d = *desc;
-    if (d.harmonics < 1) return fail(HS_ERR_ARG, "harmonics must be >= 1");
-    if (d.harmonics > HS_MAX_HARMONICS) return fail(HS_ERR_UNSUPPORTED, "harmonics above 32 not supported");
-    if (d.mode != HS_STANDARD && d.mode != HS_GREEDY) return fail(HS_ERR_ARG, "bad mode");
-    if (d.dtype != HS_F32 && d.dtype != HS_F16) return fail(HS_ERR_ARG, "bad dtype");
-    if (d.first_bin < 1) return fail(HS_ERR_ARG, "first_bin must be >= 1");
-    if (d.fundamental_end < 0) return fail(HS_ERR_ARG, "fundamental_end must be >= 0");
-    if (d.max_spectra < 1 || d.max_spectra > 65535) return fail(HS_ERR_ARG, "max_spectra out of range [1, 65535]");
-    if (d.harmonics < 64 && (d.report_mask >> d.harmonics) != 0) return fail(HS_ERR_ARG, "report_mask above H");
-    if (d.harmonic_mask != 0 && eligible_mask(d) == 0) return fail(HS_ERR_ARG, "harmonic_mask selects no k <= H");
-    if (!(d.threshold == d.threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
-    if (d.kernel < HS_KERNEL_AUTO || d.kernel > HS_KERNEL_PLAIN) return fail(HS_ERR_ARG, "bad kernel choice");
-
-    hs_plan *p = new (std::nothrow) hs_plan();
-    if (!p) return fail(HS_ERR_NOMEM, "host allocation failed");
-    p->desc = d;
-    p->hmax = bucket(d.harmonics);
-    p->max_groups = d.max_spectra;
-    int64_t parts = (int64_t)d.max_spectra * hs::kChunksBatched;
-    if (parts < hs::kChunks2D) parts = hs::kChunks2D;
-    if (parts < hs::kChunks1D) parts = hs::kChunks1D;
-    p->parts_cap = (int)parts;
-    hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) {
-        delete p;
-        return fail_hip(e, "hipGetDevice");
-    }
-    e = hipMalloc((void **)&p->norm, sizeof(hs::NormRec) * (size_t)p->max_groups);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->parts, sizeof(hs::StatPart) * (size_t)p->parts_cap);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->tickets, sizeof(uint32_t) * hs::kMaxXcd);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->prefix, sizeof(uint32_t) * ((size_t)p->max_groups + 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&p->ray, sizeof(hs::RayBand) * hs::kRayMaxBands);
-    if (e != hipSuccess) {
-        if (p->norm) (void)hipFree(p->norm);
-        if (p->parts) (void)hipFree(p->parts);
-        if (p->tickets) (void)hipFree(p->tickets);
-        if (p->prefix) (void)hipFree(p->prefix);
-        delete p;
-        (void)hipGetLastError();
-        return fail(HS_ERR_NOMEM, "device workspace allocation failed");
-    }
-    hs_status ss = setup_xcd(p);
-    if (ss != HS_OK) {
-        hs_plan_destroy(p);
-        return ss;
-    }
-    *plan = p;
+hs_status hs_plan_workspace_bytes(const hs_plan_desc *desc, size_t *bytes) {
+    if (!desc || !bytes) return fail(HS_ERR_ARG, "null argument");
+    hs_status s = check_desc(*desc);
+    if (s != HS_OK) return s;
+    *bytes = layout(*desc).total;
     return HS_OK;
+}
+
+hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
+    return create_plan(desc, nullptr, 0, plan);
+}
+
+hs_status hs_plan_create_in(const hs_plan_desc *desc, void *workspace, size_t bytes, hs_plan **plan) {
+    if (!workspace) return fail(HS_ERR_ARG, "null workspace");
+    return create_plan(desc, workspace, bytes, plan);
 }
 
 hs_status hs_plan_destroy(hs_plan *p) {
@@ -614,11 +674,7 @@ hs_status hs_plan_destroy(hs_plan *p) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
-    (void)hipFree(p->norm);
-    (void)hipFree(p->parts);
-    (void)hipFree(p->tickets);
-    (void)hipFree(p->prefix);
-    (void)hipFree(p->ray);
+    if (p->ws_owned) (void)hipFree(p->ws);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     (void)clear_graphs(p);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);

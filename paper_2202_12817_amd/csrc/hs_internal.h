@@ -194,6 +194,8 @@ struct hs_plan {
     int parts_cap;               // StatPart records available
     hs::NormRec *norm;           // device [max_groups]
     hs::StatPart *parts;         // device [parts_cap]
+    char *ws;                    // device workspace (one block; the pointers below are carved from it)
+    bool ws_owned;               // allocated by the plan (else the caller's)
     int last_groups;             // groups written by the most recent call
     uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the persistent kernel
     uint32_t *prefix;            // device [max_groups + 1] chunk prefix of the persistent kernel

@@ -23,10 +23,11 @@ HS_F32, HS_F16 = 0, 1
 HS_KERNEL_AUTO, HS_KERNEL_PERSISTENT, HS_KERNEL_PLAIN = 0, 1, 2
 HS_MAX_HARMONICS = 32
 
-EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched",
-            "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
-            "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
-            "hs_plan_tune_batched", "hs_status_string", "hs_last_error"]
+EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_create_in", "hs_plan_workspace_bytes",
+            "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16",
+            "hs_plan_set_timing", "hs_plan_get_timing", "hs_plan_set_graph", "hs_plan_graph_info",
+            "hs_plan_set_launch", "hs_plan_get_launch", "hs_plan_tune_batched", "hs_status_string",
+            "hs_last_error"]
 
 
 class HsPlanDesc(ctypes.Structure):
@@ -64,6 +65,8 @@ def load(path: str = LIB_PATH):
         lib.hs_plan_desc_init.argtypes = [ctypes.POINTER(HsPlanDesc)]
         lib.hs_plan_desc_init.restype = None
         lib.hs_plan_create.argtypes = [ctypes.POINTER(HsPlanDesc), ctypes.POINTER(vp)]
+        lib.hs_plan_create_in.argtypes = [ctypes.POINTER(HsPlanDesc), vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        lib.hs_plan_workspace_bytes.argtypes = [ctypes.POINTER(HsPlanDesc), ctypes.POINTER(ctypes.c_size_t)]
         lib.hs_plan_destroy.argtypes = [vp]
         lib.hs_sum_1d.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.hs_sum_batched.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, i64, vp, vp]
@@ -81,8 +84,8 @@ def load(path: str = LIB_PATH):
         lib.hs_status_string.restype = ctypes.c_char_p
         lib.hs_last_error.argtypes = []
         lib.hs_last_error.restype = ctypes.c_char_p
-        for name in ("hs_plan_create", "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d",
-                     "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
+        for name in ("hs_plan_create", "hs_plan_create_in", "hs_plan_workspace_bytes", "hs_plan_destroy",
+                     "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
                      "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
                      "hs_plan_tune_batched"):
             getattr(lib, name).restype = ctypes.c_int
@@ -130,6 +133,19 @@ def hs_plan_desc_init(**overrides) -> HsPlanDesc:
 def hs_plan_create(desc: HsPlanDesc) -> int:
     h = ctypes.c_void_p()
     _check(load().hs_plan_create(ctypes.byref(desc), ctypes.byref(h)), "hs_plan_create")
+    return h.value
+
+
+def hs_plan_workspace_bytes(desc: HsPlanDesc) -> int:
+    n = ctypes.c_size_t()
+    _check(load().hs_plan_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)), "hs_plan_workspace_bytes")
+    return n.value
+
+
+def hs_plan_create_in(desc: HsPlanDesc, workspace, nbytes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load().hs_plan_create_in(ctypes.byref(desc), _p(workspace), int(nbytes), ctypes.byref(h)),
+           "hs_plan_create_in")
     return h.value
 
 
@@ -217,9 +233,19 @@ def hs_last_error() -> str:
 class Plan:
     """Owns one ``hs_plan``; ``desc`` fields as keyword arguments."""
 
-    def __init__(self, **desc):
+    def __init__(self, workspace=None, **desc):
+        """``workspace``: None (the plan allocates its own) or a device buffer
+        (a torch tensor of at least ``hs_plan_workspace_bytes`` bytes, 256-byte
+        aligned) that the plan uses instead and that must outlive it."""
         self.desc = hs_plan_desc_init(**desc)
-        self.handle = hs_plan_create(self.desc)
+        if workspace is None:
+            self.handle = hs_plan_create(self.desc)
+        else:
+            nbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else None
+            if nbytes is None:
+                raise TypeError("workspace must be a device tensor")
+            self.handle = hs_plan_create_in(self.desc, workspace, nbytes)
+        self.workspace = workspace
 
     def close(self):
         if self.handle:

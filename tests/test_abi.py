@@ -85,6 +85,28 @@ def test_null_plan_and_pointers_rejected(lib):
     assert lib.hs_plan_create(None, None) == hs.HS_ERR_ARG
 
 
+def test_workspace_bytes_and_caller_workspace_checks(lib):
+    from paper_2202_12817_amd import hs
+    sizes = []
+    for b in (1, 64, 1024, 65535):
+        n = hs.hs_plan_workspace_bytes(hs.hs_plan_desc_init(max_spectra=b))
+        assert n % 256 == 0 and n > 0
+        sizes.append(n)
+    assert sizes == sorted(sizes) and sizes[-1] > sizes[0]
+    bad = hs.hs_plan_desc_init(harmonics=33)
+    n = ctypes.c_size_t()
+    assert lib.hs_plan_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
+    assert lib.hs_plan_workspace_bytes(None, ctypes.byref(n)) == hs.HS_ERR_ARG
+    d = hs.hs_plan_desc_init()
+    need = hs.hs_plan_workspace_bytes(d)
+    h = ctypes.c_void_p()
+    # rejected before any device work: NULL, misaligned or too small buffers
+    assert lib.hs_plan_create_in(ctypes.byref(d), None, need, ctypes.byref(h)) == hs.HS_ERR_ARG
+    assert lib.hs_plan_create_in(ctypes.byref(d), 4096 + 16, need, ctypes.byref(h)) == hs.HS_ERR_ARG
+    assert lib.hs_plan_create_in(ctypes.byref(d), 4096, need - 256, ctypes.byref(h)) == hs.HS_ERR_ARG
+    assert h.value is None
+
+
 def test_quantize_argument_checks(lib):
     from paper_2202_12817_amd import hs
     assert lib.hs_quantize_f16(16, 10, ctypes.c_float(0.0), 16, None) == hs.HS_ERR_ARG

@@ -220,3 +220,29 @@ def test_tuner_and_cache(dev, tmp_path):
     with hs.Plan(harmonics=H, threshold=THR, max_spectra=buf.B, kernel=hs.HS_KERNEL_PLAIN) as plan:
         with pytest.raises(hs.HsError):
             hs.hs_plan_tune_batched(plan.handle, buf.x, buf.off, buf.B, None, buf.snr, buf.harm, buf.drift)
+
+
+def test_caller_workspace(dev):
+    """A plan in a caller-owned workspace gives the same bits as a plan that
+    allocates its own; the buffer is the caller's again after destroy."""
+    hs = _hs()
+    x, off = _batch(95, B=11)
+    buf = Buffers(dev, x, off)
+    desc = dict(harmonics=H, threshold=THR, max_spectra=buf.B)
+    need = hs.hs_plan_workspace_bytes(hs.hs_plan_desc_init(**desc))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    assert ws.data_ptr() % 256 == 0
+    with hs.Plan(workspace=ws, **desc) as plan:
+        buf.call(plan)
+        torch.cuda.synchronize()
+        check_batch(buf.out(), x, off, oracle.GREEDY, "caller workspace")
+    ref = Buffers(dev, x, off)
+    with hs.Plan(**desc) as plan:
+        ref.call(plan)
+        torch.cuda.synchronize()
+    for k in ("snr", "harm", "drift"):
+        assert torch.equal(getattr(buf, k), getattr(ref, k)), k
+    ws.fill_(7)   # the workspace is the caller's again
+    torch.cuda.synchronize()
+    with pytest.raises(hs.HsError):
+        hs.Plan(workspace=ws[:need - 256], **desc)
