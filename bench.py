@@ -31,14 +31,17 @@ CALIB_BYTES = 1 << 30
 
 
 def source_hash():
-    """Hash of the HIP sources: a traffic figure is valid only for the kernel it was taken from."""
+    """Hash of what the dominant kernel is compiled from (its source, the
+    headers it includes and the build flags): a traffic figure is valid only
+    for the kernel it was taken from."""
     import hashlib
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2202_12817_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    pkg = os.path.join(ROOT, "paper_2202_12817_amd")
+    for f in (os.path.join(pkg, "csrc", "hs_sum_xcd.hip"), os.path.join(pkg, "csrc", "hs_device.h"),
+              os.path.join(pkg, "csrc", "hs_internal.h"), os.path.join(ROOT, "include", "hs.h"),
+              os.path.join(pkg, "build.py")):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
