@@ -179,6 +179,33 @@ def plane_2d_leg(hs, torch, dev, steps, warmup):
     return out
 
 
+def small_1d_leg(hs, torch, dev):
+    """Call latency of a small spectrum (65536 FP32 bins, H = 8, greedy, dense
+    outputs): six launches per call, replayed as one captured graph or not."""
+    import synthetic
+    x, _ = synthetic.config1()
+    xt = torch.from_numpy(x).to(dev)
+    snr = torch.empty(x.size, dtype=torch.float32, device=dev)
+    harm = torch.empty(x.size, dtype=torch.uint8, device=dev)
+    drift = torch.empty(x.size, dtype=torch.uint8, device=dev)
+    out = {"workload": "one spectrum of 65536 FP32 bins, H=8, greedy, dense outputs"}
+    reps = 2000
+    for name, graph, kern in (("eager_us", False, hs.HS_KERNEL_AUTO), ("graph_us", True, hs.HS_KERNEL_AUTO),
+                              ("plain_eager_us", False, hs.HS_KERNEL_PLAIN), ("plain_graph_us", True, hs.HS_KERNEL_PLAIN)):
+        plan = hs.Plan(harmonics=8, kernel=kern)
+        hs.hs_plan_set_graph(plan.handle, graph)
+        for _ in range(20):
+            hs.hs_sum_1d(plan.handle, xt, x.size, None, snr, harm, drift)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            hs.hs_sum_1d(plan.handle, xt, x.size, None, snr, harm, drift)
+        torch.cuda.synchronize()
+        out[name] = 1e6 * (time.perf_counter() - t0) / reps
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +292,7 @@ def main():
 
     in_bytes = 4 * n_bins
     lines = line_bytes_sum(lengths, H, True, 4)
+    sum_kernel = SUM_KERNEL % shape[0] if shape[0] else "k_sum_1d<32, true, false>"
     cand_bytes = 16 * min(n_cand, cap)
     sum_avg_ms = sum_ms / max(1, calls)
     norm_avg_ms = norm_ms / max(1, calls)
@@ -299,9 +327,9 @@ def main():
                    "l2_to_cu_bytes": lines, "l2_to_cu_tbs": lines / (sum_avg_ms * 1e-3) / 1e12,
                    "note": "harmonic-sum kernel: 8 B touched per greedy step (the compared pair); "
                            "min(4 k, 128) B per step at cache-line granularity"},
-        "roofline": {"bound": "hbm", "kernel": SUM_KERNEL % shape[0], "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": sum_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic(SUM_KERNEL % shape[0])},
+                     "traffic": read_traffic(sum_kernel)},
     }
 
     if args.calibration_copy:
@@ -371,6 +399,8 @@ def main():
 
     if args.plane_2d:
         result["plane_2d"] = plane_2d_leg(hs, torch, dev, args.steps, args.warmup)
+    if not args.no_extra:
+        result["small_1d"] = small_1d_leg(hs, torch, dev)
 
     if not args.no_cpu_baseline:
         import oracle

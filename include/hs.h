@@ -69,13 +69,14 @@ enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
 enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
 /* hs_plan_desc.kernel: which kernel runs.  PLAIN is the design the paper
  * describes for its GPU sum (Sec. 3.1.1): one thread per fundamental bin, a
- * grid per spectrum (per plane row in 2D).  PERSISTENT is, in 1D, the
+ * grid per spectrum (per plane row in 2D).  PERSISTENT is, for spectra, the
  * XCD-aware work-queue kernel and, in 2D, the ray-tiled kernel that stages
  * each tile's window of the plane in LDS (used when a tile of ratio width 1
  * fits its budget, about 100 rows on each side of z = 0; wider planes run
- * PLAIN).  AUTO = PERSISTENT in 1D except when partial sums are reported
- * (hs_sum_1d with report_mask), and PLAIN in 2D.  All give the same results,
- * bit for bit. */
+ * PLAIN).  AUTO = PERSISTENT for hs_sum_batched (unless the tuner picked
+ * PLAIN for the plan) and PLAIN for hs_sum_1d and hs_sum_2d (measured faster
+ * there).  hs_sum_1d with report_mask always runs PLAIN.  All give the same
+ * results, bit for bit. */
 enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
 
 #define HS_MAX_HARMONICS 32
@@ -237,10 +238,12 @@ hs_status hs_plan_graph_info(hs_plan *plan, int64_t *captures, int64_t *replays)
 /*
  * Launch shape of the persistent kernel (hs_sum_batched and the persistent
  * hs_sum_1d): fundamentals per lane (2 or 4) and resident workgroups of 256
- * threads per CU (1..4, bounded by the kernel's occupancy).  The results do
- * not depend on the shape.  Default: 4 and the occupancy limit (environment
- * HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan creation).
- * Setting a new shape drops the plan's cached graphs.
+ * threads per CU (1..4, bounded by the kernel's occupancy); for a plan with
+ * HS_KERNEL_AUTO, fundamentals_per_lane 0 makes hs_sum_batched run the plain
+ * kernel (workgroups_per_cu ignored; hs_plan_get_launch reports 0, 0).  The
+ * results do not depend on the shape.  Default: 4 and the occupancy limit
+ * (environment HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan
+ * creation).  Setting a new shape drops the plan's cached graphs.
  */
 hs_status hs_plan_set_launch(hs_plan *plan, int32_t fundamentals_per_lane, int32_t workgroups_per_cu);
 hs_status hs_plan_get_launch(hs_plan *plan, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu);
@@ -254,8 +257,9 @@ hs_status hs_plan_get_launch(hs_plan *plan, int32_t *fundamentals_per_lane, int3
  * the fastest on the plan and appends a line to cache_path (if not NULL).
  * The key is: device architecture, CU and XCD counts, harmonic bucket, mode,
  * dtype, output kind, and the powers of two below the total bins and the
- * number of spectra.  On return the outputs hold the result of a complete
- * call.  Synchronises the stream (host-blocking); HS_ERR_ARG for a plan with
+ * number of spectra.  For an HS_KERNEL_AUTO plan the plain kernel is one of
+ * the shapes.  On return the outputs hold the result of a complete call.
+ * Synchronises the stream (host-blocking); HS_ERR_ARG for a plan with
  * HS_KERNEL_PLAIN, with timing enabled, or on a capturing stream.
  */
 hs_status hs_plan_tune_batched(hs_plan *plan, const void *x, const int64_t *offsets, int32_t n_spectra,

@@ -164,7 +164,9 @@ hs_status enqueue_1d(hs_plan *p, const void *x, int64_t n_bins, const double *no
     a.drift = drift;
     a.cand = nullptr;
     a.thr = p->desc.threshold;
-    const bool plain = p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && a.partial);
+    // AUTO: the plain kernel, measured faster than the persistent one on a
+    // single spectrum at every size from 2^14 to 2^28 bins
+    const bool plain = p->desc.kernel != HS_KERNEL_PERSISTENT;
     if (plain || a.partial) {
         dim3 grid((unsigned)((n_bins + hs::kBlock - 1) / hs::kBlock), 1);
         hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
@@ -211,7 +213,7 @@ hs_status enqueue_batched(hs_plan *p, const void *x, const int64_t *offsets, int
     a.cap = cand_capacity;
     a.count = cand_count;
     a.thr = p->desc.threshold;
-    if (p->desc.kernel == HS_KERNEL_PLAIN) {
+    if (p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && p->batched_plain)) {
         dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
         e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
         if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
@@ -398,15 +400,25 @@ hs_status resident_limit(hs_plan *p, int F, int *per_cu) {
 }
 
 hs_status set_shape(hs_plan *p, int F, int wgs_per_cu) {
-    if (F != 2 && F != 4) return fail(HS_ERR_ARG, "fundamentals per lane must be 2 or 4");
+    if (F == 0) {   // the plain kernel for batches (AUTO plans)
+        if (p->desc.kernel != HS_KERNEL_AUTO) return fail(HS_ERR_ARG, "the plan fixes its kernel");
+        if (!p->batched_plain) {
+            hs_status s = clear_graphs(p);
+            if (s != HS_OK) return s;
+        }
+        p->batched_plain = true;
+        return HS_OK;
+    }
+    if (F != 2 && F != 4) return fail(HS_ERR_ARG, "fundamentals per lane must be 0, 2 or 4");
     int lim = 0;
     hs_status s = resident_limit(p, F, &lim);
     if (s != HS_OK) return s;
     if (wgs_per_cu < 1 || wgs_per_cu > lim) return fail(HS_ERR_ARG, "workgroups per CU out of range");
-    if (F != p->xcd_f || wgs_per_cu * p->n_cu != p->xcd_blocks) {
+    if (F != p->xcd_f || wgs_per_cu * p->n_cu != p->xcd_blocks || p->batched_plain) {
         s = clear_graphs(p);   // captured launches hold the old shape
         if (s != HS_OK) return s;
     }
+    p->batched_plain = false;
     p->xcd_f = F;
     p->xcd_blocks = wgs_per_cu * p->n_cu;
     return HS_OK;
@@ -484,14 +496,15 @@ hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_
         if (t0) (void)hipEventDestroy(t0);
         return fail_hip(e, "hipEventCreate");
     }
-    const int F0 = p->xcd_f, W0 = p->xcd_blocks / p->n_cu;
+    const int F0 = p->batched_plain ? 0 : p->xcd_f, W0 = p->batched_plain ? 0 : p->xcd_blocks / p->n_cu;
     int bestF = F0, bestW = W0;
     float best = 3.4e38f;
-    for (int f : {2, 4}) {
-        int lim = 0;
-        s = resident_limit(p, f, &lim);
+    for (int f : {0, 2, 4}) {
+        if (f == 0 && p->desc.kernel != HS_KERNEL_AUTO) continue;
+        int lim = 0;   // the plain kernel has one shape
+        if (f != 0) s = resident_limit(p, f, &lim);
         if (s != HS_OK) break;
-        for (int w = 1; w <= lim && s == HS_OK; ++w) {
+        for (int w = f == 0 ? 0 : 1; w <= lim && s == HS_OK; ++w) {
             s = set_shape(p, f, w);
             if (s == HS_OK) s = call();   // warm-up of this shape
             float t[3];
@@ -805,8 +818,8 @@ hs_status hs_plan_set_launch(hs_plan *p, int32_t fundamentals_per_lane, int32_t 
 
 hs_status hs_plan_get_launch(hs_plan *p, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu) {
     if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (fundamentals_per_lane) *fundamentals_per_lane = p->xcd_f;
-    if (workgroups_per_cu) *workgroups_per_cu = p->xcd_blocks / p->n_cu;
+    if (fundamentals_per_lane) *fundamentals_per_lane = p->batched_plain ? 0 : p->xcd_f;
+    if (workgroups_per_cu) *workgroups_per_cu = p->batched_plain ? 0 : p->xcd_blocks / p->n_cu;
     return HS_OK;
 }
 

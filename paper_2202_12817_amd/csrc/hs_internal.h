@@ -203,6 +203,7 @@ struct hs_plan {
     int n_cu, n_xcd;             // device shape
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel
+    bool batched_plain;          // AUTO plans: batches run the plain kernel (chosen by the tuner)
     int ray_lds;                 // LDS bytes of a tile's window in the ray-tiled plane kernel
     bool timing;                 // record stage events on every call
     std::vector<hipEvent_t> ev;  // 3 events per timed call: start, after norm, after sum

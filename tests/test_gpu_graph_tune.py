@@ -165,12 +165,12 @@ def test_launch_shapes_identical(dev):
     with hs.Plan(harmonics=H, threshold=THR, max_spectra=buf.B) as plan:
         f0, w0 = hs.hs_plan_get_launch(plan.handle)
         assert f0 in (2, 4) and 1 <= w0 <= 4
-        for F in (2, 4):
-            for Wg in (1, 2, 3, 4):
+        for F in (0, 2, 4):
+            for Wg in ((0,) if F == 0 else (1, 2, 3, 4)):
                 try:
                     hs.hs_plan_set_launch(plan.handle, F, Wg)
                 except hs.HsError:
-                    assert Wg > 1, "one workgroup per CU must always be accepted"
+                    assert Wg > 1, "one workgroup per CU (and the plain kernel) must always be accepted"
                     continue
                 assert hs.hs_plan_get_launch(plan.handle) == (F, Wg)
                 buf.call(plan)
@@ -185,7 +185,7 @@ def test_launch_shapes_identical(dev):
                         assert np.array_equal(got[k], ref[0][k]), (F, Wg, k)
                     assert np.array_equal(got["snr"].view(np.uint32), ref[0]["snr"].view(np.uint32)), (F, Wg)
                     assert n == ref[2] and _same_records(recs, ref[1]), (F, Wg)
-        for bad in ((3, 1), (4, 0), (4, 5), (0, 1)):
+        for bad in ((3, 1), (4, 0), (4, 5), (1, 1)):
             with pytest.raises(hs.HsError):
                 hs.hs_plan_set_launch(plan.handle, *bad)
 

@@ -293,16 +293,13 @@ def test_batched_max_spectra(dev):
 @pytest.mark.slow
 def test_1d_max_length(dev):
     """The longest spectrum a call accepts, 2^30 - 1 FP32 bins (4 GiB), greedy
-    H = 32, persistent kernel: exact statistics and tables, and sampled
-    fundamentals (both ends, every harmonic-count boundary, random bins)."""
+    H = 32, both kernels: exact statistics, and sampled fundamentals (both
+    ends, every harmonic-count boundary, random bins)."""
     n = (1 << 30) - 1
     x = synthetic.exp_noise(n, 93)
     print("1d max length: statistics", flush=True)
     mu1, sigma1 = oracle.norm_from_data(x, 1)
     xt = torch.from_numpy(x).to(dev)
-    got = _ops().sum_1d(xt, 32, "greedy", with_norm=True)
-    ms = _np(got["mu_sigma"])[0]
-    assert (ms[0], ms[1]) == (mu1, sigma1)
     g = np.random.default_rng(93)
     edges = [(n - 1) // (k + 1) - 1 for k in range(1, 33)]   # greedy K changes after these bins
     idx = np.unique(np.concatenate([np.arange(0, 3000), np.arange(n - 3000, n), g.integers(0, n, 20000),
@@ -310,7 +307,12 @@ def test_1d_max_length(dev):
     idx = idx[(idx >= 0) & (idx < n)]
     w = oracle.hs_1d(x, 32, oracle.GREEDY, norm=(mu1, sigma1), idx=idx)
     it = torch.from_numpy(idx).to(dev)
-    check_dense({k: got[k][it] for k in ("snr", "harm", "drift")}, w, None, "1d max length")
+    for kernel in ("plain", "persistent"):
+        got = _ops().sum_1d(xt, 32, "greedy", with_norm=True, kernel=kernel)
+        ms = _np(got["mu_sigma"])[0]
+        assert (ms[0], ms[1]) == (mu1, sigma1)
+        check_dense({k: got[k][it] for k in ("snr", "harm", "drift")}, w, None, "1d max length " + kernel)
+        del got
 
 
 # ---------------------------------------------------------------------------
