@@ -142,3 +142,23 @@ def test_product_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "hs_oracle" not in text, f
+
+
+def test_header_is_c_and_links(lib, tmp_path):
+    """include/hs.h compiles as C99 and a C program links against libhs.so and
+    calls the host-only entry points (no GPU needed)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = os.path.join(ROOT, "tests", "c_abi_check.c")
+    exe = str(tmp_path / "c_abi_check")
+    libdir = os.path.join(ROOT, "paper_2202_12817_amd")
+    cmd = [gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), src, "-o", exe,
+           "-L", libdir, "-lhs", "-Wl,-rpath," + libdir]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "19 entry points" in r.stdout
