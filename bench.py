@@ -30,18 +30,25 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sum_xcd_batched_512x_h3
 CALIB_BYTES = 1 << 30
 
 
+def _code_tokens(text):
+    """C/C++ source without comments and whitespace (comment edits do not change the kernel)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
 def source_hash():
-    """Hash of what the dominant kernel is compiled from (its source, the
-    headers it includes and the build flags): a traffic figure is valid only
-    for the kernel it was taken from."""
+    """Hash of what the dominant kernel is compiled from (its source and the
+    headers it includes, comments stripped, and the build script with its
+    flags): a traffic figure is valid only for the kernel it was taken from."""
     import hashlib
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2202_12817_amd")
     for f in (os.path.join(pkg, "csrc", "hs_sum_xcd.hip"), os.path.join(pkg, "csrc", "hs_device.h"),
-              os.path.join(pkg, "csrc", "hs_internal.h"), os.path.join(ROOT, "include", "hs.h"),
-              os.path.join(pkg, "build.py")):
+              os.path.join(pkg, "csrc", "hs_internal.h"), os.path.join(ROOT, "include", "hs.h")):
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(_code_tokens(open(f).read()).encode())
+    h.update(open(os.path.join(pkg, "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 

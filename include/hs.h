@@ -38,8 +38,9 @@
  *     library owns only the plan and its internal workspace.  Inputs must stay
  *     valid and outputs untouched until the stream has reached the end of the
  *     call.  Powers must be finite.
- *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Every
- *     call only enqueues work; it does not synchronise.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream) of the
+ *     plan's device, which must be the current device (else HS_ERR_ARG).
+ *     Every call only enqueues work; it does not synchronise.
  *   - Errors: argument checks happen before anything is enqueued and return
  *     HS_ERR_ARG / HS_ERR_UNSUPPORTED with nothing launched.  A failing HIP
  *     call returns HS_ERR_HIP.  hs_last_error() returns a message for the

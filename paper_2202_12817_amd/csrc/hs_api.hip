@@ -360,6 +360,10 @@ hs_status capture(hs_plan *p, std::vector<uint64_t> &&key, Body &body, hs_plan::
 // a capturing stream is refused: its events would time nothing).
 template <class Body>
 hs_status dispatch(hs_plan *p, std::vector<uint64_t> &&key, hipStream_t st, Body body) {
+    int cur = -1;
+    hipError_t de = hipGetDevice(&cur);
+    if (de != hipSuccess) return fail_hip(de, "hipGetDevice");
+    if (cur != p->device) return fail(HS_ERR_ARG, "the plan belongs to another device than the current one");
     if (!p->graph && !p->timing) return body(st);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(st, &cs);
