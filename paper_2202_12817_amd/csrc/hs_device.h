@@ -173,30 +173,6 @@ struct Best {
     int drift;
 };
 
-// Candidate compaction of one wave: ballot, one atomic per wave, mbcnt rank.
-__device__ __forceinline__ void emit_candidate(bool pred, uint32_t spectrum, uint32_t bin, const Best &b,
-                                               hs_candidate *cand, int64_t cap, unsigned long long *count) {
-    const uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    const int lane = __lane_id();
-    const int leader = __builtin_ctzll(mask);
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(count, (unsigned long long)__builtin_popcountll(mask));
-    base = __shfl(base, leader);
-    if (pred) {
-        const unsigned long long slot = base + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-        if ((int64_t)slot < cap) {
-            hs_candidate c;
-            c.spectrum = spectrum;
-            c.bin = bin;
-            c.snr = b.snr;
-            c.harm = (uint16_t)b.harm;
-            c.drift = (uint16_t)b.drift;
-            cand[slot] = c;
-        }
-    }
-}
-
 // Per-wave candidate staging in LDS: records are appended to the wave's own
 // slice (ballot + rank) and copied out with one global atomic per flush, so
 // the shared counter sees one atomic per slice-full instead of one per wave

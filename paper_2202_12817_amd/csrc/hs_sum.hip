@@ -60,11 +60,18 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
     return Best{kb ? best : 0.0f, kb, db};
 }
 
+// Candidate records staged per wave in LDS before one global atomic per
+// flush (a device-wide atomic per wave step serialises on one address).
+constexpr int kPlainStage = 64;
+constexpr int64_t kPlainBlocks = 8192;   // workgroups of a plain launch (32 per CU); tiles loop within
+
 // 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock
 // fundamentals, tile t = blockIdx.x + j gridDim.x.
 template <int HMAX, bool GREEDY, bool F16>
 __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
+    __shared__ hs_candidate s_stage[kBlock / 64][kPlainStage];
+    Stage st{s_stage[threadIdx.x >> 6], 0};
     const int s = blockIdx.y;
     int64_t off = 0, len = a.n_bins;
     if (a.offsets) {
@@ -101,27 +108,26 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
             if (a.harm) a.harm[off + n] = (uint8_t)b.harm;
             if (a.drift) a.drift[off + n] = (uint8_t)b.drift;
         }
-        if (a.cand) emit_candidate(in && b.harm > 0 && b.snr > a.thr, (uint32_t)s, (uint32_t)n, b, a.cand, a.cap,
-                                   a.count);
+        if (a.cand) {
+            hs_candidate rec;
+            rec.spectrum = (uint32_t)s;
+            rec.bin = (uint32_t)n;
+            rec.snr = b.snr;
+            rec.harm = (uint16_t)b.harm;
+            rec.drift = (uint16_t)b.drift;
+            stage_push<kPlainStage>(st, a.cand, a.cap, a.count, in && b.harm > 0 && b.snr > a.thr, rec);
+        }
     }
+    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
 }
 
-// f-fdot plane: blockIdx.y = row i - row0 (z = z_min + i), blockIdx.x = column tile.
+// One column tile of row i: lane owns fundamental r.
 template <int HMAX, bool GREEDY, bool F16>
-__global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
+__device__ __forceinline__ void walk_2d_tile(const Sum2dArgs &a, int i, int z, int kz, int64_t r, int valid,
+                                             const float2 *tab, Stage &st) {
     using L = Loader<F16>;
     constexpr uint32_t eb = L::kBytes;
-    const int i = a.row0 + (int)blockIdx.y;
-    const int z = a.z_min + i;
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool in = r < a.n_r;
-    const NormRec *nr = a.norm;
-    const int valid = nr->valid;
-    const float2 *tab = nr->t;
-    int kz = a.H;
-    if (z > 0) kz = a.z_max / z;
-    if (z < 0) kz = a.z_min / z;
-    if (kz > a.H) kz = a.H;
     int K = 0;
     const int64_t n_end = a.n_end < a.n_r ? a.n_end : a.n_r;
     if (in && valid && r >= a.first_bin && r < n_end) {
@@ -165,7 +171,35 @@ __global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
         if (a.harm) a.harm[o] = (uint8_t)b.harm;
         if (a.drift) a.drift[o] = (uint8_t)b.drift;
     }
-    if (a.cand) emit_candidate(in && b.harm > 0 && b.snr > a.thr, 0u, (uint32_t)o, b, a.cand, a.cap, a.count);
+    if (a.cand) {
+        hs_candidate rec;
+        rec.spectrum = 0u;
+        rec.bin = (uint32_t)o;
+        rec.snr = b.snr;
+        rec.harm = (uint16_t)b.harm;
+        rec.drift = (uint16_t)b.drift;
+        stage_push<kPlainStage>(st, a.cand, a.cap, a.count, in && b.harm > 0 && b.snr > a.thr, rec);
+    }
+}
+
+// f-fdot plane: blockIdx.y = row i - row0 (z = z_min + i); column tiles of
+// kBlock fundamentals, tile t = blockIdx.x + j gridDim.x.
+template <int HMAX, bool GREEDY, bool F16>
+__global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
+    __shared__ hs_candidate s_stage[kBlock / 64][kPlainStage];
+    Stage st{s_stage[threadIdx.x >> 6], 0};
+    const int i = a.row0 + (int)blockIdx.y;
+    const int z = a.z_min + i;
+    const NormRec *nr = a.norm;
+    const int valid = nr->valid;
+    const float2 *tab = nr->t;
+    int kz = a.H;
+    if (z > 0) kz = a.z_max / z;
+    if (z < 0) kz = a.z_min / z;
+    if (kz > a.H) kz = a.H;
+    for (int64_t t = blockIdx.x; t * kBlock < a.n_r; t += gridDim.x)
+        walk_2d_tile<HMAX, GREEDY, F16>(a, i, z, kz, t * kBlock + threadIdx.x, valid, tab, st);
+    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
 }
 
 template <int HMAX>
@@ -213,7 +247,11 @@ hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3
 }
 
 hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st) {
-    dim3 grid((unsigned)((a.n_r + kBlock - 1) / kBlock), (unsigned)rows);
+    // about kPlainBlocks workgroups in all, each looping over column tiles
+    const int64_t tiles = (a.n_r + kBlock - 1) / kBlock;
+    int64_t per_row = (kPlainBlocks + rows - 1) / rows;
+    if (per_row > tiles) per_row = tiles;
+    dim3 grid((unsigned)per_row, (unsigned)rows);
     switch (hmax) {
         case 4: return sum2d_h<4>(a, greedy, f16, grid, st);
         case 8: return sum2d_h<8>(a, greedy, f16, grid, st);
