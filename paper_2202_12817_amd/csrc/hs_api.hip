@@ -169,7 +169,7 @@ hs_status enqueue_1d(hs_plan *p, const void *x, int64_t n_bins, const double *no
     const bool plain = p->desc.kernel != HS_KERNEL_PERSISTENT;
     if (plain || a.partial) {
         int64_t blocks = (n_bins + hs::kBlock - 1) / hs::kBlock;   // tiles loop within the grid
-        if (blocks > 8192) blocks = 8192;
+        if (blocks > hs::kPlainBlocks) blocks = hs::kPlainBlocks;
         dim3 grid((unsigned)blocks, 1);
         hipError_t e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
         if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");

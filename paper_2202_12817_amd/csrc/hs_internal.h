@@ -15,6 +15,8 @@ constexpr int kChunksBatched = 64;   // statistics chunks per spectrum of a batc
 constexpr int kChunks1D = 512;       // statistics chunks of a single spectrum
 constexpr int kChunks2D = 2048;      // statistics chunks of a plane
 constexpr int kTileBlocksBatched = 96;   // plain kernel: blocks per spectrum of a batch
+constexpr int64_t kPlainBlocks = 32768;  // plain kernel: most workgroups of a 1D or plane launch (tiles loop
+                                         // within; 16k..128k measured alike on the plane workload)
 constexpr int kMaxXcd = 64;              // work-queue counters in the plan workspace
 
 // Where the statistics of group g (spectrum or plane) come from: `rows` rows

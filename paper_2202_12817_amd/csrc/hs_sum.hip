@@ -63,7 +63,6 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
 // Candidate records staged per wave in LDS before one global atomic per
 // flush (a device-wide atomic per wave step serialises on one address).
 constexpr int kPlainStage = 64;
-constexpr int64_t kPlainBlocks = 8192;   // workgroups of a plain launch (32 per CU); tiles loop within
 
 // 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock
 // fundamentals, tile t = blockIdx.x + j gridDim.x.
