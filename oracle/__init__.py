@@ -22,7 +22,9 @@ What it computes, in the paper's order:
    ``nm_k = float(-(mu_k / sigma_k))``, each rounded once from float64.
 3. The per-fundamental sums and the best SNR (``hs_oracle.c``): simple sum,
    Sec. 3.1 Eq. (3); greedy sum, Sec. 3.3 Eq. (5) and Algorithm 2; running
-   maximum of the partial-sum SNRs, Eq. (2).
+   maximum of the partial-sum SNRs, Eq. (2).  The PRESTO-style comparators of
+   Sec. 3.2 (Eq. (4), Algorithm 1: PRESTO, PRESTO_all, PRESTO+) are indexed by
+   the last bin of the series: stage K sums the bins nearest to ``h n / K``.
 4. Candidates: every bin whose best SNR is strictly above a threshold.
 
 Precision ``"f32"`` mirrors the precision of the GPU's decisions (float sums
@@ -42,11 +44,14 @@ import numpy as np
 __all__ = [
     "build", "exact_sums", "stats", "norm_from_data", "tables", "is_degenerate",
     "keff", "hs_1d", "hs_2d", "hs_batched", "candidates", "quantize_f16",
-    "GREEDY", "STANDARD",
+    "GREEDY", "STANDARD", "PRESTO", "PRESTO_ALL", "PRESTO_PLUS", "presto_stages",
 ]
 
 STANDARD = 0
 GREEDY = 1
+PRESTO = 2        # Sec. 3.2: power-of-two stages, fundamental + even harmonics
+PRESTO_ALL = 3    # Sec. 3.2 / Sec. 5: power-of-two stages, every harmonic
+PRESTO_PLUS = 4   # Sec. 3.2 / Sec. 5: every stage 1..H, every harmonic
 MAX_H = 64
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,7 +83,10 @@ def _load():
         lib.hso_1d_f64.argtypes = [p, i64, i32, i32, i64, i64, u64, p, p, p, i64, p, p, p, i32, p, p]
         lib.hso_2d_f32.argtypes = [p, i64, i64, i32, i32, i32, i32, i64, i64, u64, p, p, p, i64, p, p, p]
         lib.hso_2d_f64.argtypes = [p, i64, i64, i32, i32, i32, i32, i64, i64, u64, p, p, p, i64, p, p, p]
-        for f in (lib.hso_1d_f32, lib.hso_1d_f64, lib.hso_2d_f32, lib.hso_2d_f64):
+        lib.hso_presto_f32.argtypes = [p, i64, i32, i32, i64, i64, u64, p, p, p, i64, p, p]
+        lib.hso_presto_f64.argtypes = [p, i64, i32, i32, i64, i64, u64, p, p, p, i64, p, p]
+        for f in (lib.hso_1d_f32, lib.hso_1d_f64, lib.hso_2d_f32, lib.hso_2d_f64,
+                  lib.hso_presto_f32, lib.hso_presto_f64):
             f.restype = None
         _lib = lib
     return _lib
@@ -191,10 +199,31 @@ def _kmask(mask: int, H: int) -> int:
     return ((1 << H) - 1) if not mask else (mask & ((1 << H) - 1))
 
 
-def _check(H, mode):
+def presto_stages(n: int, H: int, mode: int, first_bin: int = 1):
+    """Stages ``(K, m)`` formed for last bin ``n`` (``m`` = elements summed).
+
+    Sec. 3.2: PRESTO takes the power-of-two orders from 2 and sums the
+    fundamental and the even harmonics (m = 1 + K/2); PRESTO_all the same
+    orders with every harmonic; PRESTO+ every order 1..H with every harmonic.
+    A stage is formed only if its fundamental, the bin nearest to n / K, is
+    not below ``first_bin``.
+    """
+    out = []
+    if n < first_bin:
+        return out
+    for K in range(1, H + 1):
+        if mode != PRESTO_PLUS and not (K >= 2 and K & (K - 1) == 0):
+            continue
+        if (2 * n + K) // (2 * K) < first_bin:
+            continue
+        out.append((K, 1 + K // 2 if mode == PRESTO else K))
+    return out
+
+
+def _check(H, mode, modes=(STANDARD, GREEDY, PRESTO, PRESTO_ALL, PRESTO_PLUS)):
     if not (1 <= H <= MAX_H):
         raise ValueError("H out of range")
-    if mode not in (STANDARD, GREEDY):
+    if mode not in modes:
         raise ValueError("bad mode")
 
 
@@ -205,10 +234,16 @@ def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
     ``norm``: ``(mu1, sigma1)`` to use instead of the statistics of ``x``.
     ``idx``: fundamentals to evaluate (default: every bin, output index = bin).
     ``report``: harmonic counts K whose partial sums are returned (zero where a
-    fundamental sums fewer than K harmonics).
+    fundamental sums fewer than K harmonics; simple and greedy sums only).
+    PRESTO modes: the output index is the last bin of the series, ``harm`` the
+    order K of the best stage and ``drift`` zero; ``fundamental_end`` bounds
+    the last bin.
     Returns a dict with ``snr``, ``harm``, ``drift``, ``partial``, ``mu1``, ``sigma1``.
     """
     _check(H, mode)
+    presto = mode in (PRESTO, PRESTO_ALL, PRESTO_PLUS)
+    if presto and len(list(report)):
+        raise ValueError("partial sums are reported for the simple and greedy sums only")
     x = np.ascontiguousarray(x, dtype=np.float32)
     N = x.size
     if norm is None:
@@ -229,8 +264,13 @@ def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
     mu, sig, rs, nm = tables(mu1, sigma1, H)
     n_end = N if not fundamental_end else min(N, int(fundamental_end))
     lib = _load()
-    fn = lib.hso_1d_f64 if f64 else lib.hso_1d_f32
     t1, t2 = (mu, sig) if f64 else (rs, nm)
+    if presto:
+        fn = lib.hso_presto_f64 if f64 else lib.hso_presto_f32
+        fn(_ptr(x), N, H, mode, int(first_bin), n_end, _kmask(harmonic_mask, H), _ptr(t1), _ptr(t2),
+           _ptr(idx_a), n_out, _ptr(snr), _ptr(harm))
+        return out
+    fn = lib.hso_1d_f64 if f64 else lib.hso_1d_f32
     fn(_ptr(x), N, H, mode, int(first_bin), n_end, _kmask(harmonic_mask, H), _ptr(t1), _ptr(t2),
        _ptr(idx_a), n_out, _ptr(snr), _ptr(harm), _ptr(drift), len(rep),
        _ptr(rep) if len(rep) else None, _ptr(partial))
@@ -246,7 +286,7 @@ def hs_2d(plane, z_min, z_max, H, mode, *, first_bin=1, fundamental_end=0,
     Statistics cover the whole plane (columns ``>= first_bin``).
     ``idx``: flat fundamentals ``i n_r + r`` (default: all).
     """
-    _check(H, mode)
+    _check(H, mode, (STANDARD, GREEDY))
     p = np.ascontiguousarray(plane, dtype=np.float32)
     n_z, n_r = p.shape
     if n_z != z_max - z_min + 1:

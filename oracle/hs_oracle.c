@@ -15,7 +15,9 @@
  *     compares x[n] and x[n + 1]);
  *   - the SNR of every partial sum and the running maximum, Sec. 2, Eq. (2),
  *     normalised with the mean and standard deviation of a partial sum of k
- *     elements (tables computed by the Python side of the oracle).
+ *     elements (tables computed by the Python side of the oracle);
+ *   - the PRESTO-style sums the paper compares against, Sec. 3.2, Eq. (4) and
+ *     Algorithm 1 (PRESTO, PRESTO_all, PRESTO+), at the end of this file.
  *
  * Two precisions:
  *   f32: the partial sums are accumulated in float in harmonic order and the
@@ -244,5 +246,105 @@ void hso_2d_f64(const float *plane, int64_t n_r, int64_t stride, int32_t z_min, 
         }
         one_f64(rows, n_r, r, K, greedy, kmask, mu, sig, snr + o, harm + o, drift + o,
                 0, NULL, NULL, 0);
+    }
+}
+
+/*
+ * PRESTO-style sums (Sec. 3.2, Eq. (4), Algorithm 1), indexed by the LAST bin
+ * n of a harmonic series rather than by its fundamental.  Stage K (harmonic
+ * order K) sums the bins nearest to h n / K for the harmonics h it includes,
+ * in increasing h, and forms one SNR when the stage is complete.  Readings:
+ *   - "Round": nearest integer, halves rounded up: floor((2 h n + K) / (2 K));
+ *   - variant 2 (PRESTO): stages K = 2, 4, 8, ... <= H, harmonics h = 1 and
+ *     the even h <= K (the paper's PRESTO sums only the even harmonics above
+ *     the fundamental);
+ *     variant 3 (PRESTO_all): the same stages, every harmonic h = 1..K;
+ *     variant 4 (PRESTO+): every stage K = 1..H, every harmonic h = 1..K;
+ *   - a stage of m summed elements is normalised with the m-element mean and
+ *     standard deviation (Eq. (2)), so a PRESTO stage K uses m = 1 + K/2;
+ *   - stage K is formed only if its fundamental bin, the lowest bin it reads,
+ *     is >= first_bin; the highest bin it reads is n itself;
+ *   - the best stage: the largest SNR among the stages selected by kmask
+ *     (bit K-1), ties to the smaller K; harm = its K (its fundamental is the
+ *     bin nearest to n / K), 0 when no stage was formed.
+ */
+#define HSO_PRESTO 2
+#define HSO_PRESTO_ALL 3
+#define HSO_PRESTO_PLUS 4
+
+/* The bin nearest to h n / K, halves rounded up. */
+static int64_t nearest_bin(int64_t h, int64_t n, int64_t K)
+{
+    return (2 * h * n + K) / (2 * K);
+}
+
+static int stage_formed(int32_t variant, int64_t K)
+{
+    if (variant == HSO_PRESTO_PLUS) return 1;
+    return K >= 2 && (K & (K - 1)) == 0;     /* powers of two from 2 */
+}
+
+static int harmonic_summed(int32_t variant, int64_t h)
+{
+    return variant != HSO_PRESTO || h == 1 || h % 2 == 0;
+}
+
+void hso_presto_f32(const float *x, int64_t len, int32_t H, int32_t variant,
+                    int64_t first_bin, int64_t n_end, uint64_t kmask,
+                    const float *rs, const float *nm, const int64_t *idx, int64_t n_out,
+                    float *snr, uint8_t *harm)
+{
+    if (H < 1 || H > HS_ORACLE_MAX_H) abort();
+    if (variant < HSO_PRESTO || variant > HSO_PRESTO_PLUS) abort();
+    for (int64_t o = 0; o < n_out; ++o) {
+        int64_t n = idx ? idx[o] : o;
+        float best = 0.0f;
+        int32_t kb = 0;
+        for (int64_t K = 1; K <= H && n >= first_bin && n < n_end; ++K) {
+            if (!stage_formed(variant, K) || nearest_bin(1, n, K) < first_bin) continue;
+            float S = 0.0f;
+            int64_t m = 0;
+            for (int64_t h = 1; h <= K; ++h) {
+                if (!harmonic_summed(variant, h)) continue;
+                S = S + rd32(x, len, nearest_bin(h, n, K));
+                m += 1;
+            }
+            float v = fmaf(S, rs[m - 1], nm[m - 1]);
+            if ((kmask >> (K - 1)) & 1u) {
+                if (kb == 0 || v > best) { best = v; kb = (int32_t)K; }
+            }
+        }
+        snr[o] = kb ? best : 0.0f;
+        harm[o] = (uint8_t)kb;
+    }
+}
+
+void hso_presto_f64(const float *x, int64_t len, int32_t H, int32_t variant,
+                    int64_t first_bin, int64_t n_end, uint64_t kmask,
+                    const double *mu, const double *sig, const int64_t *idx, int64_t n_out,
+                    double *snr, uint8_t *harm)
+{
+    if (H < 1 || H > HS_ORACLE_MAX_H) abort();
+    if (variant < HSO_PRESTO || variant > HSO_PRESTO_PLUS) abort();
+    for (int64_t o = 0; o < n_out; ++o) {
+        int64_t n = idx ? idx[o] : o;
+        double best = 0.0;
+        int32_t kb = 0;
+        for (int64_t K = 1; K <= H && n >= first_bin && n < n_end; ++K) {
+            if (!stage_formed(variant, K) || nearest_bin(1, n, K) < first_bin) continue;
+            double S = 0.0;
+            int64_t m = 0;
+            for (int64_t h = 1; h <= K; ++h) {
+                if (!harmonic_summed(variant, h)) continue;
+                S = S + rd32(x, len, nearest_bin(h, n, K));
+                m += 1;
+            }
+            double v = (S - mu[m - 1]) / sig[m - 1];
+            if ((kmask >> (K - 1)) & 1u) {
+                if (kb == 0 || v > best) { best = v; kb = (int32_t)K; }
+            }
+        }
+        snr[o] = kb ? best : 0.0;
+        harm[o] = (uint8_t)kb;
     }
 }

@@ -54,3 +54,31 @@ def read_2d(name="hand_2d.txt"):
     zs = sorted(rows)
     plane = np.array([rows[z] for z in zs], dtype=np.float32)
     return plane, zs[0], zs[-1], cases
+
+
+def read_presto(name="hand_presto.txt"):
+    """Spectra, stage cases and the last-bin examples of the PRESTO-style sums."""
+    spectra, cases, lastbins = {}, [], []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "spectrum":
+                spectra[tok[1]] = np.array([float(v) for v in tok[2:]], dtype=np.float32)
+            elif tok[0] == "lastbin":
+                kv = _kv(tok[1:])
+                lastbins.append(dict(n=int(kv["n"]), K=int(kv["K"]), fundamental=int(kv["fundamental"])))
+            elif tok[0] == "pcase":
+                kv = _kv(tok[3:])
+                mask = 0 if kv["mask"] == "all" else sum(1 << (k - 1) for k in _ints(kv["mask"]))
+                stages = []
+                for s in kv["stages"].split(","):
+                    if s:
+                        K, S, m = (int(v) for v in s.split(":"))
+                        stages.append((K, S, m))
+                cases.append(dict(spectrum=tok[1], mode=tok[2], H=int(kv["H"]), mask=mask,
+                                  first=int(kv["first"]), n=int(kv["n"]), stages=stages,
+                                  harm=int(kv["harm"])))
+    return spectra, cases, lastbins

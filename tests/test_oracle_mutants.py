@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hs_oracle.c")
 PINS = ["tests/test_oracle_golden.py", "tests/test_oracle_stats.py", "tests/test_oracle_bruteforce.py",
-        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py"]
+        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py", "tests/test_oracle_presto.py"]
 
 C_MUTANTS = {
     "greedy-tie-moves": ("if (b > a) { d += 1; v = b; }", "if (b >= a) { d += 1; v = b; }"),
@@ -27,6 +27,16 @@ C_MUTANTS = {
     "no-drift-in-sum": ("{ d += 1; v = b; } else { v = a; }", "{ d += 1; v = a; } else { v = a; }"),
     "2d-row-not-scaled": ("int64_t row = k * z - z_min;", "int64_t row = z - z_min;"),
     "drift-before-step": ("kb = (int32_t)k; db = (int32_t)d;", "kb = (int32_t)k; db = (int32_t)(d > 0 ? d - 1 : 0);"),
+    "presto-round-down": ("return (2 * h * n + K) / (2 * K);", "return (2 * h * n) / (2 * K);"),
+    "presto-half-down": ("return (2 * h * n + K) / (2 * K);", "return (2 * h * n + K - 1) / (2 * K);"),
+    "presto-odd-harmonics": ("h == 1 || h % 2 == 0;", "h == 1 || h % 2 == 1;"),
+    "presto-f32-norm-by-order": ("rs[m - 1], nm[m - 1]", "rs[K - 1], nm[K - 1]"),
+    "presto-f64-norm-by-order": ("mu[m - 1]) / sig[m - 1]", "mu[K - 1]) / sig[K - 1]"),
+    "presto-stage-one": ("return K >= 2 && (K & (K - 1)) == 0;", "return (K & (K - 1)) == 0;"),
+    "presto-first-bin-ignored": ("nearest_bin(1, n, K) < first_bin", "nearest_bin(1, n, K) < 0"),
+    "presto-tie-to-larger-stage": ("v > best) { best = v; kb = (int32_t)K; }", "v >= best) { best = v; kb = (int32_t)K; }"),
+    "presto-dropped-term": ("S = S + rd32(x, len, nearest_bin(h, n, K));", "S = rd32(x, len, nearest_bin(h, n, K));"),
+    "presto-reversed-order": ("rd32(x, len, nearest_bin(h, n, K))", "rd32(x, len, nearest_bin(K + 1 - h, n, K))"),
 }
 
 PY_MUTANTS = {
