@@ -186,6 +186,62 @@ def plane_2d_leg(hs, torch, dev, steps, warmup):
     return out
 
 
+# Table 2 of the paper (V100, sum kernels only, 1024 spectra of 2^17 bins):
+# fundamental bins per second, in Gbin/s.  Context, not a target.
+PAPER_TABLE2_GBINS = {"greedy": {32: 8.64, 16: 14.70, 8: 26.10, 4: 39.9},
+                      "presto": {32: 9.64, 16: 15.24, 8: 23.38, 4: 37.49},
+                      "presto_plus": {32: 1.16, 16: 3.79, 8: 11.03, 4: 26.80}}
+
+
+def table2_leg(hs, torch, dev, steps, warmup):
+    """The paper's performance comparison (Sec. 4.3, Table 2): 1024 spectra of
+    2^17 FP32 bins, dense snr/harm outputs, greedy vs PRESTO vs PRESTO+ (and
+    PRESTO_all) at H = 4, 8, 16, 32; bins per second of the harmonic-sum kernel
+    (the statistics stage, shared by all algorithms, reported beside it)."""
+    import synthetic
+    x, off = synthetic.table2(threads=16)
+    B, n_bins = off.size - 1, int(x.size)
+    xt, ot = torch.from_numpy(x).to(dev), torch.from_numpy(off).to(dev)
+    del x
+    snr = torch.empty(n_bins, dtype=torch.float32, device=dev)
+    harm = torch.empty(n_bins, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "%d spectra of %d FP32 bins (Exp(1) noise + 5 pulse trains each), dense snr/harm"
+                       % (B, n_bins // B),
+           "unit": "Gbin/s (all bins / harmonic-sum kernel time)", "paper_v100_gbin_s": PAPER_TABLE2_GBINS}
+    modes = (("greedy", hs.HS_GREEDY), ("presto", hs.HS_PRESTO), ("presto_all", hs.HS_PRESTO_ALL),
+             ("presto_plus", hs.HS_PRESTO_PLUS))
+    for mname, mode in modes:
+        res = {}
+        for h in (4, 8, 16, 32):
+            plan = hs.Plan(harmonics=h, mode=mode, dtype=hs.HS_F32, max_spectra=B)
+            if mode == hs.HS_GREEDY:
+                hs.hs_plan_tune_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, None, stream)
+            for _ in range(warmup):
+                hs.hs_sum_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, stream)
+            torch.cuda.synchronize()
+            hs.hs_plan_set_timing(plan.handle, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                hs.hs_sum_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, stream)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            c, nm, sm = hs.hs_plan_get_timing(plan.handle)
+            plan.close()
+            sum_ms = sm / max(1, c)
+            r = {"gbin_s": n_bins / (sum_ms * 1e-3) / 1e9, "sum_ms": sum_ms,
+                 "normalisation_ms": nm / max(1, c), "call_ms": 1e3 * el,
+                 "gbin_s_whole_call": n_bins / el / 1e9,
+                 "sum_kernel_gbs_compulsory": n_bins * 9 / (sum_ms * 1e-3) / 1e9}
+            paper = PAPER_TABLE2_GBINS.get(mname, {}).get(h)
+            if paper:
+                r["ratio_to_paper_v100"] = r["gbin_s"] / paper
+            res["H%d" % h] = r
+        out[mname] = res
+    del xt, snr, harm
+    return out
+
+
 def small_1d_leg(hs, torch, dev):
     """Call latency of a small spectrum (65536 FP32 bins, H = 8, greedy, dense
     outputs): six launches per call, replayed as one captured graph or not."""
@@ -408,6 +464,7 @@ def main():
         result["plane_2d"] = plane_2d_leg(hs, torch, dev, args.steps, args.warmup)
     if not args.no_extra:
         result["small_1d"] = small_1d_leg(hs, torch, dev)
+        result["table2"] = table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -14,6 +14,22 @@
  *       x[k n + d] and x[k n + d + 1]; when the second is strictly larger the
  *       drift d grows by one.  Step k = 1 compares x[n] and x[n + 1].
  *
+ *   The PRESTO-style comparators (Sec. 3.2, Eq. (4), Algorithm 1) index the
+ *   output by the LAST bin n of a series instead: stage K (harmonic order K)
+ *   sums the bins nearest to h n / K (halves rounded up), in increasing h,
+ *   and forms one SNR from its m-element sum:
+ *     - HS_PRESTO:      K = 2, 4, 8, ... <= H; h = 1 and the even h <= K
+ *                       (m = 1 + K/2);
+ *     - HS_PRESTO_ALL:  the same K; every h = 1..K (m = K);
+ *     - HS_PRESTO_PLUS: every K = 1..H; every h = 1..K (m = K).
+ *   A stage is formed only if its fundamental (the bin nearest to n / K) is
+ *   >= first_bin.  harm = the order K of the best stage (its fundamental is
+ *   the bin nearest to n / harm), drift = 0, harmonic_mask bit K-1 selects
+ *   stage K, fundamental_end bounds the last bin.  These modes run one kernel
+ *   (kernel AUTO or PLAIN), support hs_sum_1d without report_mask and
+ *   hs_sum_batched, and return HS_ERR_UNSUPPORTED from hs_sum_2d, the launch
+ *   shape calls and the tuner.
+ *
  * Conventions shared by every entry point:
  *
  *   - Normalisation (reading of Eq. (2) and GetMeanStdev of Algorithms 1-2):
@@ -66,7 +82,8 @@ typedef enum hs_status {
     HS_ERR_NOMEM = 4         /* device allocation of the plan workspace failed */
 } hs_status;
 
-enum { HS_STANDARD = 0, HS_GREEDY = 1 };   /* hs_plan_desc.mode */
+enum { HS_STANDARD = 0, HS_GREEDY = 1,          /* hs_plan_desc.mode */
+       HS_PRESTO = 2, HS_PRESTO_ALL = 3, HS_PRESTO_PLUS = 4 };
 enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power type */
 /* hs_plan_desc.kernel: which kernel runs.  PLAIN is the design the paper
  * describes for its GPU sum (Sec. 3.1.1): one thread per fundamental bin, a
@@ -85,7 +102,7 @@ enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
 /* Plan parameters.  Fill with hs_plan_desc_init, then override. */
 typedef struct hs_plan_desc {
     int32_t  harmonics;        /* H, 1..HS_MAX_HARMONICS (default 32) */
-    int32_t  mode;             /* HS_STANDARD or HS_GREEDY (default HS_GREEDY) */
+    int32_t  mode;             /* HS_STANDARD, HS_GREEDY (default) or a PRESTO mode */
     int32_t  dtype;            /* HS_F32 or HS_F16 (IEEE binary16 storage, decoded exactly) */
     int32_t  first_bin;        /* >= 1; lowest fundamental and lowest bin in the statistics (default 1) */
     uint64_t harmonic_mask;    /* bit k-1 set: the k-harmonic sum competes for the best; 0 = all (default) */
@@ -99,7 +116,7 @@ typedef struct hs_plan_desc {
 /* One candidate: a bin whose best SNR is strictly above the threshold. */
 typedef struct hs_candidate {
     uint32_t spectrum;   /* index of the spectrum (0 for hs_sum_2d) */
-    uint32_t bin;        /* fundamental bin n (hs_sum_2d: row * n_r + column) */
+    uint32_t bin;        /* fundamental bin n (PRESTO modes: last bin; hs_sum_2d: row * n_r + column) */
     float    snr;        /* best SNR */
     uint16_t harm;       /* harmonic count of the best partial sum */
     uint16_t drift;      /* drift after that harmonic */

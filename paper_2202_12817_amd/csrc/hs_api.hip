@@ -39,6 +39,9 @@ uint64_t eligible_mask(const hs_plan_desc &d) {
     return d.harmonic_mask ? (d.harmonic_mask & all) : all;
 }
 
+// The PRESTO-style comparators (last-bin indexing, one kernel).
+bool is_presto(int mode) { return mode == HS_PRESTO || mode == HS_PRESTO_ALL || mode == HS_PRESTO_PLUS; }
+
 int64_t n_end_of(const hs_plan_desc &d, int64_t len) {
     return d.fundamental_end > 0 && d.fundamental_end < len ? d.fundamental_end : len;
 }
@@ -167,7 +170,13 @@ hs_status enqueue_1d(hs_plan *p, const void *x, int64_t n_bins, const double *no
     // AUTO: the plain kernel, measured faster than the persistent one on a
     // single spectrum at every size from 2^14 to 2^28 bins
     const bool plain = p->desc.kernel != HS_KERNEL_PERSISTENT;
-    if (plain || a.partial) {
+    if (is_presto(p->desc.mode)) {
+        int64_t blocks = (n_bins + hs::kBlock - 1) / hs::kBlock;
+        if (blocks > hs::kPlainBlocks) blocks = hs::kPlainBlocks;
+        hipError_t e = hs::launch_presto(a, p->hmax, p->desc.mode, p->desc.dtype == HS_F16, dim3((unsigned)blocks, 1),
+                                         st);
+        if (e != hipSuccess) return fail_hip(e, "PRESTO-style sum kernel");
+    } else if (plain || a.partial) {
         int64_t blocks = (n_bins + hs::kBlock - 1) / hs::kBlock;   // tiles loop within the grid
         if (blocks > hs::kPlainBlocks) blocks = hs::kPlainBlocks;
         dim3 grid((unsigned)blocks, 1);
@@ -215,7 +224,11 @@ hs_status enqueue_batched(hs_plan *p, const void *x, const int64_t *offsets, int
     a.cap = cand_capacity;
     a.count = cand_count;
     a.thr = p->desc.threshold;
-    if (p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && p->batched_plain)) {
+    if (is_presto(p->desc.mode)) {
+        e = hs::launch_presto(a, p->hmax, p->desc.mode, p->desc.dtype == HS_F16,
+                              dim3(hs::kTileBlocksBatched, (unsigned)n_spectra), st);
+        if (e != hipSuccess) return fail_hip(e, "PRESTO-style sum kernel");
+    } else if (p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && p->batched_plain)) {
         dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
         e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
         if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
@@ -559,7 +572,7 @@ hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_
 hs_status check_desc(const hs_plan_desc &d) {
     if (d.harmonics < 1) return fail(HS_ERR_ARG, "harmonics must be >= 1");
     if (d.harmonics > HS_MAX_HARMONICS) return fail(HS_ERR_UNSUPPORTED, "harmonics above 32 not supported");
-    if (d.mode != HS_STANDARD && d.mode != HS_GREEDY) return fail(HS_ERR_ARG, "bad mode");
+    if (d.mode != HS_STANDARD && d.mode != HS_GREEDY && !is_presto(d.mode)) return fail(HS_ERR_ARG, "bad mode");
     if (d.dtype != HS_F32 && d.dtype != HS_F16) return fail(HS_ERR_ARG, "bad dtype");
     if (d.first_bin < 1) return fail(HS_ERR_ARG, "first_bin must be >= 1");
     if (d.fundamental_end < 0) return fail(HS_ERR_ARG, "fundamental_end must be >= 0");
@@ -568,6 +581,10 @@ hs_status check_desc(const hs_plan_desc &d) {
     if (d.harmonic_mask != 0 && eligible_mask(d) == 0) return fail(HS_ERR_ARG, "harmonic_mask selects no k <= H");
     if (!(d.threshold == d.threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
     if (d.kernel < HS_KERNEL_AUTO || d.kernel > HS_KERNEL_PLAIN) return fail(HS_ERR_ARG, "bad kernel choice");
+    if (is_presto(d.mode) && d.report_mask != 0)
+        return fail(HS_ERR_UNSUPPORTED, "partial sums are reported for the simple and greedy sums only");
+    if (is_presto(d.mode) && d.kernel == HS_KERNEL_PERSISTENT)
+        return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have one kernel (AUTO or PLAIN)");
     return HS_OK;
 }
 
@@ -736,6 +753,7 @@ hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stri
                     const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
                     int64_t cand_capacity, unsigned long long *cand_count, void *stream) {
     if (!p || !plane) return fail(HS_ERR_ARG, "null argument");
+    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "no f-fdot form of the PRESTO-style sums");
     if (n_r < 2 || n_r >= (1ll << 30)) return fail(HS_ERR_ARG, "n_r out of range [2, 2^30)");
     if (row_stride < n_r) return fail(HS_ERR_ARG, "row_stride < n_r");
     if (z_max < z_min) return fail(HS_ERR_ARG, "z_max < z_min");
@@ -819,6 +837,7 @@ hs_status hs_plan_graph_info(hs_plan *p, int64_t *captures, int64_t *replays) {
 
 hs_status hs_plan_set_launch(hs_plan *p, int32_t fundamentals_per_lane, int32_t workgroups_per_cu) {
     if (!p) return fail(HS_ERR_ARG, "null plan");
+    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
     return set_shape(p, fundamentals_per_lane, workgroups_per_cu);
 }
 
@@ -834,6 +853,7 @@ hs_status hs_plan_tune_batched(hs_plan *p, const void *x, const int64_t *offsets
                                int64_t cand_capacity, unsigned long long *cand_count, const char *cache_path,
                                void *stream) {
     if (!p) return fail(HS_ERR_ARG, "null plan");
+    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
     if (p->timing) return fail(HS_ERR_ARG, "stage timing is enabled");
     hipStream_t st = (hipStream_t)stream;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

@@ -183,6 +183,7 @@ hipError_t launch_quantize_f16(const float *x, int64_t n, float scale, uint16_t 
 hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3 grid, hipStream_t st);
 hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st);
 hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, int n_cu, hipStream_t st);
+hipError_t launch_presto(const SumArgs &a, int hmax, int variant, bool f16, dim3 grid, hipStream_t st);
 
 }  // namespace hs
 

@@ -1,0 +1,196 @@
+// PRESTO-style harmonic sums (gfx950): the comparators of Sec. 3.2 (Eq. (4),
+// Algorithm 1).  The output index n is the LAST bin of a harmonic series:
+// stage K (harmonic order K) sums the bins nearest to h n / K (halves rounded
+// up) for its harmonics h, in increasing h, and forms one SNR (Eq. (2)) from
+// the stage's m-element sum:
+//   HS_PRESTO:      K = 2, 4, 8, ...; h = 1 and the even h <= K; m = 1 + K/2
+//   HS_PRESTO_ALL:  K = 2, 4, 8, ...; h = 1..K;                    m = K
+//   HS_PRESTO_PLUS: K = 1..H;         h = 1..K;                    m = K
+// A stage is formed only while its fundamental, the bin nearest to n / K, is
+// >= first_bin (it only falls as K grows, so the first unformed stage ends
+// the walk); the best stage is the largest SNR among the stages the mask
+// selects, ties to the smaller K.
+//
+// One lane owns one last bin n.  With n = Q K + R (0 <= R < K) the bin of
+// harmonic h is  h Q + floor((2 h R + K) / (2 K)):  h Q and 2 h R + K are
+// carried from one harmonic to the next by additions, and the small quotient
+// (numerator 2 h R + K <= 2 K^2 - K < 2^11) is floor(x ceil(2^20 / 2K) / 2^20),
+// exact for every numerator below 2^11 and every K <= 32 (checked
+// exhaustively), taken as the high word of a 24-bit multiply.  K is a
+// compile-time constant in every stage, so n / K is a multiply-high or a
+// shift.  Consecutive lanes own consecutive
+// bins; harmonic h of a wave reads about 64 h / K consecutive bins, so every
+// gather is nearly contiguous.
+#include "hs_internal.h"
+
+namespace hs {
+namespace {
+
+template <int VARIANT, int K>
+constexpr bool stage_formed() {
+    return VARIANT == HS_PRESTO_PLUS || (K >= 2 && (K & (K - 1)) == 0);
+}
+
+template <int VARIANT>
+constexpr bool harmonic_summed(int h) {
+    return VARIANT != HS_PRESTO || h == 1 || h % 2 == 0;
+}
+
+template <int VARIANT, int K>
+constexpr int stage_elems() {
+    return VARIANT == HS_PRESTO ? 1 + K / 2 : K;
+}
+
+// floor(x / (2 K)) for x < 2^11, given x12 = x 2^12 (< 2^23): the high word
+// of the 24 x 24-bit product x12 ceil(2^20 / (2 K)), one full-rate multiply.
+template <int K>
+__device__ __forceinline__ uint32_t div_2k(uint32_t x12) {
+    constexpr uint32_t M = ((1u << 20) + 2 * K - 1) / (2 * K);
+    static_assert(K >= 1 && K <= 32, "stage order out of range");
+    uint32_t q;
+    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(q) : "s"(M), "v"(x12));
+    return q;
+}
+
+template <bool F16>
+__device__ __forceinline__ float load_at(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    if constexpr (F16) {
+        unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte_off, 0, 0);
+        return (float)__builtin_bit_cast(_Float16, b);
+    } else {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+    }
+}
+
+struct StageState {
+    float best;
+    int kb;
+    bool live;    // every earlier stage's fundamental was >= first_bin
+};
+
+// Stage K of last bin n.
+template <int VARIANT, bool F16, int K>
+__device__ __forceinline__ void stage(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
+                                      const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
+    if constexpr (stage_formed<VARIANT, K>()) {
+        if (!s.live || K > H) return;
+        constexpr uint32_t eb = F16 ? 2u : 4u;
+        constexpr uint32_t sh = F16 ? 1u : 2u;
+        static_assert(2 * K * K - K < (1 << 11), "2 h R + K must stay below 2^11");
+        const uint32_t Q = n / (uint32_t)K;
+        const uint32_t R2 = (2u * (n - Q * (uint32_t)K)) << 12;   // step of (2 h R + K) 2^12
+        const uint32_t Qb = Q * eb;                               // step of h Q, in bytes
+        uint32_t hqb = Qb;                                        // h = 1
+        uint32_t hr = R2 + ((uint32_t)K << 12);
+        const uint32_t fd = div_2k<K>(hr);
+        if (Q + fd < first_bin) {     // the fundamental
+            s.live = false;
+            return;
+        }
+        float S = load_at<F16>(r, hqb + (fd << sh));
+#pragma unroll
+        for (int h = 2; h <= K; ++h) {
+            // carried by additions (kept opaque so that they stay one add each)
+            hqb += Qb;
+            hr += R2;
+            asm("" : "+v"(hqb), "+v"(hr));
+            if (!harmonic_summed<VARIANT>(h)) continue;
+            S = S + load_at<F16>(r, hqb + (div_2k<K>(hr) << sh));
+        }
+        constexpr int m = stage_elems<VARIANT, K>();
+        const float2 t = tab[m - 1];
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        if ((kmask >> (K - 1)) & 1ull) {
+            if (s.kb == 0 || snr > s.best) {
+                s.best = snr;
+                s.kb = K;
+            }
+        }
+    }
+}
+
+template <int VARIANT, bool F16, int K, int HMAX>
+__device__ __forceinline__ void stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
+                                       const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
+    stage<VARIANT, F16, K>(r, n, H, first_bin, tab, kmask, s);
+    if constexpr (K < HMAX) stages<VARIANT, F16, K + 1, HMAX>(r, n, H, first_bin, tab, kmask, s);
+}
+
+constexpr int kPrestoStage = 64;   // candidate records staged per wave
+
+// 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock last
+// bins, tile t = blockIdx.x + j gridDim.x.
+template <int HMAX, int VARIANT, bool F16>
+__global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
+    constexpr uint32_t eb = F16 ? 2u : 4u;
+    __shared__ hs_candidate s_stage[kBlock / 64][kPrestoStage];
+    Stage st{s_stage[threadIdx.x >> 6], 0};
+    const int sp = blockIdx.y;
+    int64_t off = 0, len = a.n_bins;
+    if (a.offsets) {
+        off = a.offsets[sp];
+        len = a.offsets[sp + 1] - off;
+        if (len < 0 || len >= (1ll << 30)) len = 0;   // malformed offsets: no output, no read
+    }
+    const NormRec *nr = a.norm + sp;
+    const int valid = nr->valid;
+    const float2 *tab = nr->t;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const char *)a.x + off * eb, (uint32_t)(len * eb));
+    const int64_t n_end = a.n_end < len ? a.n_end : len;
+    for (int64_t t = blockIdx.x; t * kBlock < len; t += gridDim.x) {
+        const int64_t n = t * kBlock + threadIdx.x;
+        const bool in = n < len;
+        StageState s{0.0f, 0, true};
+        if (in && valid && n >= a.first_bin && n < n_end)
+            stages<VARIANT, F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
+        const float snr = s.kb ? s.best : 0.0f;
+        if (in) {
+            if (a.snr) a.snr[off + n] = snr;
+            if (a.harm) a.harm[off + n] = (uint8_t)s.kb;
+            if (a.drift) a.drift[off + n] = 0;
+        }
+        if (a.cand) {
+            hs_candidate rec;
+            rec.spectrum = (uint32_t)sp;
+            rec.bin = (uint32_t)n;
+            rec.snr = snr;
+            rec.harm = (uint16_t)s.kb;
+            rec.drift = 0;
+            stage_push<kPrestoStage>(st, a.cand, a.cap, a.count, in && s.kb > 0 && snr > a.thr, rec);
+        }
+    }
+    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
+}
+
+template <int HMAX, int VARIANT>
+hipError_t presto_v(const SumArgs &a, bool f16, dim3 grid, hipStream_t st) {
+    if (f16)
+        hipLaunchKernelGGL((k_presto<HMAX, VARIANT, true>), grid, dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_presto<HMAX, VARIANT, false>), grid, dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int HMAX>
+hipError_t presto_h(const SumArgs &a, int variant, bool f16, dim3 grid, hipStream_t st) {
+    switch (variant) {
+        case HS_PRESTO: return presto_v<HMAX, HS_PRESTO>(a, f16, grid, st);
+        case HS_PRESTO_ALL: return presto_v<HMAX, HS_PRESTO_ALL>(a, f16, grid, st);
+        case HS_PRESTO_PLUS: return presto_v<HMAX, HS_PRESTO_PLUS>(a, f16, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_presto(const SumArgs &a, int hmax, int variant, bool f16, dim3 grid, hipStream_t st) {
+    switch (hmax) {
+        case 4: return presto_h<4>(a, variant, f16, grid, st);
+        case 8: return presto_h<8>(a, variant, f16, grid, st);
+        case 16: return presto_h<16>(a, variant, f16, grid, st);
+        case 32: return presto_h<32>(a, variant, f16, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hs

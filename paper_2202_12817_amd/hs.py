@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libhs.so")
 
 HS_OK, HS_ERR_ARG, HS_ERR_UNSUPPORTED, HS_ERR_HIP, HS_ERR_NOMEM = 0, 1, 2, 3, 4
 HS_STANDARD, HS_GREEDY = 0, 1
+HS_PRESTO, HS_PRESTO_ALL, HS_PRESTO_PLUS = 2, 3, 4
 HS_F32, HS_F16 = 0, 1
 HS_KERNEL_AUTO, HS_KERNEL_PERSISTENT, HS_KERNEL_PLAIN = 0, 1, 2
 HS_MAX_HARMONICS = 32

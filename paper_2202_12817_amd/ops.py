@@ -9,8 +9,9 @@ import torch
 
 from . import hs
 
-_MODES = {"standard": hs.HS_STANDARD, "greedy": hs.HS_GREEDY, hs.HS_STANDARD: hs.HS_STANDARD,
-          hs.HS_GREEDY: hs.HS_GREEDY}
+_MODES = {"standard": hs.HS_STANDARD, "greedy": hs.HS_GREEDY, "presto": hs.HS_PRESTO,
+          "presto_all": hs.HS_PRESTO_ALL, "presto_plus": hs.HS_PRESTO_PLUS}
+_MODES.update({v: v for v in list(_MODES.values())})
 
 
 def _dtype_code(t: torch.Tensor) -> int:

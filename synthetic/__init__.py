@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "rng", "exp_noise", "gaussian_weights", "train_amplitude", "inject_train",
     "random_trains", "config1", "config2", "config3_lengths", "config3_spectrum",
-    "config3", "config4", "inject_track", "random_tracks",
+    "config3", "config4", "inject_track", "random_tracks", "table2",
 ]
 
 
@@ -192,3 +192,10 @@ def config4(n_r: int = 1 << 21, z_min: int = -100, z_max: int = 100, seed: int =
         w = gaussian_weights(duty, 4 * max_harm)
         inject_track(plane, z_min, r0, z0, w, train_amplitude(w[:max_harm], snr))
     return plane, tracks
+
+
+def table2(n_spectra: int = 1024, length: int = 131072, seed: int = 5, threads: int = 8):
+    """The shape of the paper's performance comparison (Sec. 4.3: 1024 power
+    spectra of 2^17 bins each): noise and trains drawn as for the batched
+    workload, every spectrum ``length`` bins.  Returns (x, offsets)."""
+    return config3(n_spectra=n_spectra, lo=length, hi=length, seed=seed, threads=threads)

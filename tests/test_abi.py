@@ -66,6 +66,22 @@ def test_plan_create_rejects_bad_desc(lib, field, value, status):
     assert lib.hs_last_error()
 
 
+def test_presto_modes_validation(lib):
+    # the PRESTO-style modes accept the plain kernel only and report no partial sums
+    from paper_2202_12817_amd import hs
+    n = ctypes.c_size_t()
+    for mode in (hs.HS_PRESTO, hs.HS_PRESTO_ALL, hs.HS_PRESTO_PLUS):
+        for kernel in (hs.HS_KERNEL_AUTO, hs.HS_KERNEL_PLAIN):
+            d = hs.hs_plan_desc_init(mode=mode, kernel=kernel)
+            assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_OK
+        d = hs.hs_plan_desc_init(mode=mode, kernel=hs.HS_KERNEL_PERSISTENT)
+        assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
+        d = hs.hs_plan_desc_init(mode=mode, report_mask=1)
+        assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
+    d = hs.hs_plan_desc_init(mode=5)
+    assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_ARG
+
+
 def test_masks_must_fit_h(lib):
     from paper_2202_12817_amd import hs
     h = ctypes.c_void_p()
