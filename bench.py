@@ -37,19 +37,39 @@ def _code_tokens(text):
     return "".join(text.split())
 
 
-def source_hash():
-    """Hash of what the dominant kernel is compiled from (its source and the
-    headers it includes, comments stripped, and the build script with its
-    flags): a traffic figure is valid only for the kernel it was taken from."""
+def source_hash(kernel_file="hs_sum_xcd.hip"):
+    """Hash of what a kernel is compiled from (its source and the headers it
+    includes, comments stripped, and the build script with its flags): a
+    counter figure is valid only for the kernel it was taken from."""
     import hashlib
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2202_12817_amd")
-    for f in (os.path.join(pkg, "csrc", "hs_sum_xcd.hip"), os.path.join(pkg, "csrc", "hs_device.h"),
+    for f in (os.path.join(pkg, "csrc", kernel_file), os.path.join(pkg, "csrc", "hs_device.h"),
               os.path.join(pkg, "csrc", "hs_internal.h"), os.path.join(ROOT, "include", "hs.h")):
         h.update(os.path.basename(f).encode())
         h.update(_code_tokens(open(f).read()).encode())
     h.update(open(os.path.join(pkg, "build.py"), "rb").read())
     return h.hexdigest()[:16]
+
+
+TABLE2_FILE = os.path.join(ROOT, "profiles", "table2_1024x131072_greedy_presto.txt")
+VALU_PEAK = 256 * 2.4e9      # wave instructions per second: 256 CUs, one VALU wave instruction per clock
+
+
+def table2_counters():
+    """Per-kernel counters (VALU instructions, HBM-side bytes per dispatch) of the
+    Table 2 workload from the committed rocprofv3 summary, for the kernels whose
+    sources still match."""
+    out = {}
+    try:
+        for line in open(TABLE2_FILE):
+            if line.startswith("json: "):
+                rec = json.loads(line[6:])
+                if rec.get("source") == source_hash(rec.get("file", "")):
+                    out[(rec["algorithm"], rec["H"])] = rec
+    except (OSError, KeyError, ValueError):
+        pass
+    return out
 
 
 def read_traffic(kernel):
@@ -209,6 +229,7 @@ def table2_leg(hs, torch, dev, steps, warmup):
     out = {"workload": "%d spectra of %d FP32 bins (Exp(1) noise + 5 pulse trains each), dense snr/harm"
                        % (B, n_bins // B),
            "unit": "Gbin/s (all bins / harmonic-sum kernel time)", "paper_v100_gbin_s": PAPER_TABLE2_GBINS}
+    counters = table2_counters()
     modes = (("greedy", hs.HS_GREEDY), ("presto", hs.HS_PRESTO), ("presto_all", hs.HS_PRESTO_ALL),
              ("presto_plus", hs.HS_PRESTO_PLUS))
     for mname, mode in modes:
@@ -229,10 +250,23 @@ def table2_leg(hs, torch, dev, steps, warmup):
             c, nm, sm = hs.hs_plan_get_timing(plan.handle)
             plan.close()
             sum_ms = sm / max(1, c)
+            comp = n_bins * 9      # 4 B read, 4 + 1 B written per bin
             r = {"gbin_s": n_bins / (sum_ms * 1e-3) / 1e9, "sum_ms": sum_ms,
                  "normalisation_ms": nm / max(1, c), "call_ms": 1e3 * el,
                  "gbin_s_whole_call": n_bins / el / 1e9,
-                 "sum_kernel_gbs_compulsory": n_bins * 9 / (sum_ms * 1e-3) / 1e9}
+                 "sum_kernel_gbs_compulsory": comp / (sum_ms * 1e-3) / 1e9}
+            rec = counters.get((mname, h))
+            hbm_frac = comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+            if rec:
+                valu_rate = rec["valu"] / (sum_ms * 1e-3)
+                alu = valu_rate / VALU_PEAK > hbm_frac
+                r["roofline"] = {"bound": "alu" if alu else "hbm", "kernel": rec["kernel"],
+                                 "achieved": valu_rate / 1e9 if alu else comp / (sum_ms * 1e-3) / 1e9,
+                                 "peak": VALU_PEAK / 1e9 if alu else HBM_PEAK_GBS,
+                                 "unit": "G VALU wave-instructions/s" if alu else "GB/s",
+                                 "frac": valu_rate / VALU_PEAK if alu else hbm_frac,
+                                 "valu_frac": valu_rate / VALU_PEAK, "hbm_frac_compulsory": hbm_frac,
+                                 "traffic": rec["fetch_bytes"] + rec["write_bytes"]}
             paper = PAPER_TABLE2_GBINS.get(mname, {}).get(h)
             if paper:
                 r["ratio_to_paper_v100"] = r["gbin_s"] / paper
@@ -269,6 +303,16 @@ def small_1d_leg(hs, torch, dev):
     return out
 
 
+def calibration_copy(torch, dev):
+    """An elementwise negation that reads and writes CALIB_BYTES once; its
+    kernel name ("neg") identifies it in the counter output."""
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +326,8 @@ def main():
     ap.add_argument("--launch", default=None, metavar="F,W",
                     help="fixed launch shape (fundamentals per lane, workgroups per CU) instead of tuning")
     ap.add_argument("--plane-2d", action="store_true", help="also time the f-fdot plane (2^21 x 201, H=16)")
+    ap.add_argument("--leg", choices=["table2", "plane_2d"], default=None,
+                    help="run only this leg and print its JSON object (profiling aid)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a 1 GiB read + 1 GiB write elementwise kernel (reference for rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
@@ -301,6 +347,13 @@ def main():
     from paper_2202_12817_amd import hs
 
     dev = torch.device("cuda:0")
+    if args.leg:
+        if args.calibration_copy:
+            calibration_copy(torch, dev)
+        legs = {"table2": lambda: table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup),
+                "plane_2d": lambda: plane_2d_leg(hs, torch, dev, args.steps, args.warmup)}
+        print(json.dumps({args.leg: legs[args.leg]()}))
+        return
     x, off = synthetic.config3(n_spectra=args.spectra, threads=16)
     lengths = np.diff(off)
     n_bins = int(x.size)
@@ -396,13 +449,7 @@ def main():
     }
 
     if args.calibration_copy:
-        # an elementwise negation reads and writes CALIB_BYTES once; its kernel
-        # name ("neg") identifies it in the counter output
-        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(torch, dev)
 
     if not args.no_extra:
         # plain: one hs_sum_1d per spectrum, dense outputs, no graph

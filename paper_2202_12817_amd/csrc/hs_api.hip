@@ -133,6 +133,10 @@ hs_status setup_xcd(hs_plan *p) {
     // overrides: 4096..61440, so that window and staging stay below 64 KiB)
     const int rl = env_int("HS_RAY_LDS", hs::kRayLdsBytes);
     p->ray_lds = rl >= 4096 && rl <= 61440 ? rl : hs::kRayLdsBytes;
+    // workgroups per spectrum of the batched plain launches (HS_TILE_BLOCKS
+    // overrides: 8..4096)
+    const int tb = env_int("HS_TILE_BLOCKS", hs::kTileBlocksBatched);
+    p->tile_blocks = tb >= 8 && tb <= 4096 ? tb : hs::kTileBlocksBatched;
     return HS_OK;
 }
 
@@ -224,12 +228,13 @@ hs_status enqueue_batched(hs_plan *p, const void *x, const int64_t *offsets, int
     a.cap = cand_capacity;
     a.count = cand_count;
     a.thr = p->desc.threshold;
+    a.n_xcd = p->n_xcd;
     if (is_presto(p->desc.mode)) {
         e = hs::launch_presto(a, p->hmax, p->desc.mode, p->desc.dtype == HS_F16,
-                              dim3(hs::kTileBlocksBatched, (unsigned)n_spectra), st);
+                              dim3((unsigned)p->tile_blocks, (unsigned)n_spectra), st);
         if (e != hipSuccess) return fail_hip(e, "PRESTO-style sum kernel");
     } else if (p->desc.kernel == HS_KERNEL_PLAIN || (p->desc.kernel == HS_KERNEL_AUTO && p->batched_plain)) {
-        dim3 grid(hs::kTileBlocksBatched, (unsigned)n_spectra);
+        dim3 grid((unsigned)p->tile_blocks, (unsigned)n_spectra);
         e = hs::launch_sum_1d(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, grid, st);
         if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
     } else {

@@ -55,7 +55,23 @@ struct SumArgs {
     int64_t cap;
     unsigned long long *count;
     float thr;
+    int32_t n_xcd;            // batched plain launches: XCDs the workgroups are dealt to (1: no remap)
 };
+
+// Workgroup (blockIdx.x, blockIdx.y) of a (gridDim.x, gridDim.y) grid as
+// (tile block, spectrum) of a batched plain launch.  The dispatcher deals
+// workgroups to the XCDs in turn by linear id, so workgroup L runs on XCD
+// L mod n_xcd; renumbering L to (L mod n_xcd) (T / n_xcd) + L / n_xcd gives
+// each XCD a contiguous run of whole spectra, which it walks in order, so
+// one XCD's L2 holds the harmonic windows of a few spectra instead of every
+// XCD holding a slice of every spectrum.  A bijection: results do not change.
+__device__ __forceinline__ void batched_block(int n_xcd, int *bx, int *spectrum) {
+    const uint32_t gx = gridDim.x, T = gridDim.x * gridDim.y;
+    uint32_t L = blockIdx.x + blockIdx.y * gx;
+    if (n_xcd > 1 && T % (uint32_t)n_xcd == 0) L = (L % (uint32_t)n_xcd) * (T / (uint32_t)n_xcd) + L / (uint32_t)n_xcd;
+    *bx = (int)(L % gx);
+    *spectrum = (int)(L / gx);
+}
 
 // Harmonic sum over an f-fdot plane.
 struct Sum2dArgs {
@@ -207,6 +223,7 @@ struct hs_plan {
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel
     bool batched_plain;          // AUTO plans: batches run the plain kernel (chosen by the tuner)
+    int tile_blocks;             // batched plain launches: workgroups per spectrum
     int ray_lds;                 // LDS bytes of a tile's window in the ray-tiled plane kernel
     bool timing;                 // record stage events on every call
     std::vector<hipEvent_t> ev;  // 3 events per timed call: start, after norm, after sum

@@ -118,14 +118,16 @@ __device__ __forceinline__ void stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int
 
 constexpr int kPrestoStage = 64;   // candidate records staged per wave
 
-// 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock last
-// bins, tile t = blockIdx.x + j gridDim.x.
+// 1D spectra: workgroup -> (tile block bx, spectrum sp) by batched_block
+// (sp = 0 for one spectrum); tiles of kBlock last bins, tile
+// t = bx + j gridDim.x.
 template <int HMAX, int VARIANT, bool F16>
 __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
     constexpr uint32_t eb = F16 ? 2u : 4u;
     __shared__ hs_candidate s_stage[kBlock / 64][kPrestoStage];
     Stage st{s_stage[threadIdx.x >> 6], 0};
-    const int sp = blockIdx.y;
+    int bx, sp;
+    batched_block(a.n_xcd, &bx, &sp);
     int64_t off = 0, len = a.n_bins;
     if (a.offsets) {
         off = a.offsets[sp];
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
     const float2 *tab = nr->t;
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const char *)a.x + off * eb, (uint32_t)(len * eb));
     const int64_t n_end = a.n_end < len ? a.n_end : len;
-    for (int64_t t = blockIdx.x; t * kBlock < len; t += gridDim.x) {
+    for (int64_t t = bx; t * kBlock < len; t += gridDim.x) {
         const int64_t n = t * kBlock + threadIdx.x;
         const bool in = n < len;
         StageState s{0.0f, 0, true};

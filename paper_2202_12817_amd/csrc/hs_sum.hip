@@ -64,14 +64,16 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
 // flush (a device-wide atomic per wave step serialises on one address).
 constexpr int kPlainStage = 64;
 
-// 1D spectra: blockIdx.y = spectrum (batched) or 0; tiles of kBlock
-// fundamentals, tile t = blockIdx.x + j gridDim.x.
+// 1D spectra: workgroup -> (tile block bx, spectrum s) by batched_block
+// (s = 0 for one spectrum); tiles of kBlock fundamentals, tile
+// t = bx + j gridDim.x.
 template <int HMAX, bool GREEDY, bool F16>
 __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
     __shared__ hs_candidate s_stage[kBlock / 64][kPlainStage];
     Stage st{s_stage[threadIdx.x >> 6], 0};
-    const int s = blockIdx.y;
+    int bx, s;
+    batched_block(a.n_xcd, &bx, &s);
     int64_t off = 0, len = a.n_bins;
     if (a.offsets) {
         off = a.offsets[s];
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     const char *base = (const char *)a.x + off * eb;
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(base, (uint32_t)(len * eb));
     const int64_t n_end = a.n_end < len ? a.n_end : len;
-    for (int64_t t = blockIdx.x; t * kBlock < len; t += gridDim.x) {
+    for (int64_t t = bx; t * kBlock < len; t += gridDim.x) {
         const int64_t n = t * kBlock + threadIdx.x;
         const bool in = n < len;
         int K = 0;
