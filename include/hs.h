@@ -207,6 +207,36 @@ hs_status hs_sum_2d(hs_plan *plan, const void *plane, int64_t n_r, int64_t row_s
                     unsigned long long *cand_count, void *stream);
 
 /*
+ * Equal-length spectra in the interleaved layout of Sec. 3.1.1 (the same bin
+ * of different spectra side by side): bin m of spectrum s at
+ * x[m * n_spectra + s].  Each spectrum (column) gets its own statistics and
+ * the sums of the plan's mode (HS_STANDARD or HS_GREEDY; others return
+ * HS_ERR_UNSUPPORTED), bit for bit those of hs_sum_batched on the same
+ * spectra stored one after another.  The plan's kernel choice is ignored.
+ *   x          [n_bins][n_spectra] powers, dtype of the plan; n_bins >= 2,
+ *              n_bins * n_spectra < 2^30, 1 <= n_spectra <= max_spectra.
+ *   norm       NULL or [2 n_spectra] doubles (mu1, sigma1 per spectrum).
+ *   snr/harm/drift  NULL, or dense [n_bins][n_spectra] outputs (interleaved
+ *              like x); drift may be NULL.
+ *   cand/cand_capacity/cand_count  as for hs_sum_batched (spectrum = s,
+ *              bin = m).  At least one of snr or cand must be given.
+ */
+hs_status hs_sum_interleaved(hs_plan *plan, const void *x, int64_t n_bins, int32_t n_spectra,
+                             const double *norm, float *snr, uint8_t *harm, uint8_t *drift,
+                             hs_candidate *cand, int64_t cand_capacity,
+                             unsigned long long *cand_count, void *stream);
+
+/*
+ * The transpose into the interleaved layout (the preprocessing that
+ * Sec. 3.1.1 says the layout costs): out[m * n_spectra + s] = x[s * n_bins + m]
+ * for n_spectra spectra of n_bins elements of elem_bytes (2 or 4) bytes.
+ * Device buffers of n_bins * n_spectra elements that must not overlap;
+ * stream-ordered like the sum calls.  No plan needed.
+ */
+hs_status hs_interleave(const void *x, int64_t n_bins, int32_t n_spectra, int32_t elem_bytes,
+                        void *out, void *stream);
+
+/*
  * Export the normalisation used by the most recent sum call on this plan
  * (stream-ordered device-to-device copy of its first n entries).
  *   mu_sigma  [2 n] doubles (mu1, sigma1); tables NULL or [n][2][H] floats

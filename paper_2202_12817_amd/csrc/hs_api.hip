@@ -90,7 +90,8 @@ hs_status run_norm(hs_plan *p, hs::StatsArgs sa, int groups, hipStream_t st) {
     sa.norm = p->norm;
     if (sa.user_norm == nullptr) {
         if ((int64_t)groups * sa.chunks > p->parts_cap) return fail(HS_ERR_ARG, "too many statistics chunks");
-        e = hs::launch_stats(sa, groups, p->desc.dtype == HS_F16, st);
+        e = sa.il_spectra ? hs::launch_stats_il(sa, p->desc.dtype == HS_F16, st)
+                          : hs::launch_stats(sa, groups, p->desc.dtype == HS_F16, st);
         if (e != hipSuccess) return fail_hip(e, "statistics kernel");
     }
     e = hs::launch_finalize(sa, groups, st);
@@ -309,6 +310,56 @@ hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_str
         e = hs::launch_sum_2d(a, p->hmax, greedy, f16, (int)n_z, st);
     }
     if (e != hipSuccess) return fail_hip(e, "harmonic-sum kernel");
+    return mark(p, 2, st);
+}
+
+// Equal-length spectra in the interleaved layout: statistics per spectrum
+// (column), then one launch of the interleaved walk.
+constexpr int kIlTile = 32;   // fundamentals per wave task of the interleaved walk
+
+hs_status enqueue_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t n_spectra, const double *norm,
+                              float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
+                              unsigned long long *cand_count, hipStream_t st) {
+    hipError_t e;
+    if (cand) {
+        e = hs::launch_zero_u64(cand_count, st);
+        if (e != hipSuccess) return fail_hip(e, "counter reset");
+    }
+    hs::StatsArgs sa{};
+    sa.x = x;
+    sa.offsets = nullptr;
+    sa.n_bins = n_bins;
+    sa.rows = 1;
+    sa.row_len = n_bins;
+    sa.stride = n_bins;
+    sa.first_bin = p->desc.first_bin;
+    sa.chunks = hs::kChunksBatched;
+    sa.user_norm = norm;
+    sa.il_spectra = n_spectra;
+    hs_status s = run_norm(p, sa, n_spectra, st);
+    if (s != HS_OK) return s;
+    hs::IlArgs a{};
+    a.x = x;
+    a.n_bins = n_bins;
+    a.n_spectra = n_spectra;
+    a.norm = p->norm;
+    a.first_bin = p->desc.first_bin;
+    a.H = p->desc.harmonics;
+    a.n_end = n_end_of(p->desc, n_bins);
+    a.kmask = eligible_mask(p->desc);
+    a.snr = snr;
+    a.harm = harm;
+    a.drift = drift;
+    a.cand = cand;
+    a.cap = cand_capacity;
+    a.count = cand_count;
+    a.thr = p->desc.threshold;
+    a.n_groups = (n_spectra + 63) / 64;
+    a.tile = kIlTile;
+    a.n_tasks = (int64_t)a.n_groups * ((n_bins + kIlTile - 1) / kIlTile);
+    a.n_xcd = p->n_xcd;
+    e = hs::launch_sum_il(a, p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, st);
+    if (e != hipSuccess) return fail_hip(e, "interleaved harmonic-sum kernel");
     return mark(p, 2, st);
 }
 
@@ -778,6 +829,44 @@ hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stri
                         return enqueue_2d(p, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand,
                                           cand_capacity, cand_count, s);
                     });
+}
+
+hs_status hs_sum_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t n_spectra, const double *norm,
+                             float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
+                             unsigned long long *cand_count, void *stream) {
+    if (!p || !x) return fail(HS_ERR_ARG, "null argument");
+    if (p->desc.mode != HS_STANDARD && p->desc.mode != HS_GREEDY)
+        return fail(HS_ERR_UNSUPPORTED, "the interleaved layout runs the simple and greedy sums");
+    if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
+    if (n_bins < 2 || n_bins * (int64_t)n_spectra >= (1ll << 30))
+        return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30 / n_spectra)");
+    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
+    if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
+    if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
+    if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
+    hipStream_t st = (hipStream_t)stream;
+    return dispatch(p,
+                    {4, W(x), (uint64_t)n_bins, (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
+                     (uint64_t)cand_capacity, W(cand_count)},
+                    st, [=](hipStream_t s) {
+                        return enqueue_interleaved(p, x, n_bins, n_spectra, norm, snr, harm, drift, cand,
+                                                   cand_capacity, cand_count, s);
+                    });
+}
+
+hs_status hs_interleave(const void *x, int64_t n_bins, int32_t n_spectra, int32_t elem_bytes, void *out,
+                        void *stream) {
+    if (!x || !out) return fail(HS_ERR_ARG, "null argument");
+    if (elem_bytes != 2 && elem_bytes != 4) return fail(HS_ERR_ARG, "elem_bytes must be 2 or 4");
+    if (n_bins < 1 || n_spectra < 1 || n_spectra > 65535 * 64 || (n_bins + 63) / 64 > 0x7fffffffll)
+        return fail(HS_ERR_ARG, "sizes out of range");
+    if (((uintptr_t)x | (uintptr_t)out) & (uintptr_t)(elem_bytes - 1)) return fail(HS_ERR_ARG, "misaligned buffer");
+    const char *xb = (const char *)x, *ob = (const char *)out;
+    const int64_t bytes = n_bins * n_spectra * (int64_t)elem_bytes;
+    if (xb < ob + bytes && ob < xb + bytes) return fail(HS_ERR_ARG, "x and out overlap");
+    hipError_t e = hs::launch_interleave(x, n_bins, n_spectra, elem_bytes, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "interleave kernel");
+    return HS_OK;
 }
 
 hs_status hs_get_norm(hs_plan *p, int32_t n, double *mu_sigma, float *tables, int32_t *valid, void *stream) {

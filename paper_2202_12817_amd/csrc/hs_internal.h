@@ -34,6 +34,7 @@ struct StatsArgs {
     StatPart *parts;          // [groups][chunks]
     NormRec *norm;            // [groups]
     const double *user_norm;  // NULL or [2 groups] (mu1, sigma1)
+    int32_t il_spectra;       // interleaved layout: spectra per row (group g = spectrum g of n_bins bins)
 };
 
 // Harmonic sum over 1D spectra (one, or a batch through `offsets`).
@@ -92,6 +93,30 @@ struct Sum2dArgs {
     int64_t cap;
     unsigned long long *count;
     float thr;
+};
+
+// Harmonic sum over equal-length spectra in the interleaved layout
+// x[m n_spectra + s] (see hs_interleaved.hip).
+struct IlArgs {
+    const void *x;
+    int64_t n_bins;
+    int32_t n_spectra;
+    const NormRec *norm;      // [n_spectra]
+    int32_t first_bin;
+    int32_t H;
+    int64_t n_end;
+    uint64_t kmask;
+    float *snr;               // NULL or [n_bins][n_spectra]
+    uint8_t *harm;
+    uint8_t *drift;
+    hs_candidate *cand;
+    int64_t cap;
+    unsigned long long *count;
+    float thr;
+    int32_t n_groups;         // spectra groups of 64 lanes
+    int32_t tile;             // fundamentals per wave task
+    int64_t n_tasks;          // n_groups * tiles
+    int32_t n_xcd;
 };
 
 // Persistent XCD-aware batched harmonic sum (see hs_sum_xcd.hip).
@@ -200,6 +225,9 @@ hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3
 hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, int rows, hipStream_t st);
 hipError_t launch_sum_2d_ray(Ray2dArgs a, int hmax, bool greedy, bool f16, int n_cu, hipStream_t st);
 hipError_t launch_presto(const SumArgs &a, int hmax, int variant, bool f16, dim3 grid, hipStream_t st);
+hipError_t launch_stats_il(const StatsArgs &a, bool f16, hipStream_t st);
+hipError_t launch_sum_il(const IlArgs &a, int hmax, bool greedy, bool f16, hipStream_t st);
+hipError_t launch_interleave(const void *x, int64_t n_bins, int n_spectra, int elem_bytes, void *out, hipStream_t st);
 
 }  // namespace hs
 

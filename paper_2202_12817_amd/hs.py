@@ -28,7 +28,7 @@ EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_create_in", "hs_plan
             "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16",
             "hs_plan_set_timing", "hs_plan_get_timing", "hs_plan_set_graph", "hs_plan_graph_info",
             "hs_plan_set_launch", "hs_plan_get_launch", "hs_plan_tune_batched", "hs_status_string",
-            "hs_last_error"]
+            "hs_last_error", "hs_sum_interleaved", "hs_interleave"]
 
 
 class HsPlanDesc(ctypes.Structure):
@@ -73,6 +73,8 @@ def load(path: str = LIB_PATH):
         lib.hs_sum_batched.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         lib.hs_sum_2d.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         lib.hs_get_norm.argtypes = [vp, i32, vp, vp, vp, vp]
+        lib.hs_sum_interleaved.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        lib.hs_interleave.argtypes = [vp, i64, i32, i32, vp, vp]
         lib.hs_quantize_f16.argtypes = [vp, i64, ctypes.c_float, vp, vp]
         lib.hs_plan_set_timing.argtypes = [vp, i32]
         lib.hs_plan_get_timing.argtypes = [vp, vp, vp, vp]
@@ -88,7 +90,7 @@ def load(path: str = LIB_PATH):
         for name in ("hs_plan_create", "hs_plan_create_in", "hs_plan_workspace_bytes", "hs_plan_destroy",
                      "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
                      "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
-                     "hs_plan_tune_batched"):
+                     "hs_plan_tune_batched", "hs_sum_interleaved", "hs_interleave"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -171,6 +173,18 @@ def hs_sum_2d(plan, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift
     _check(load().hs_sum_2d(plan, _p(plane), int(n_r), int(row_stride), int(z_min), int(z_max), _p(norm),
                             _p(snr), _p(harm), _p(drift), _p(cand), int(cand_capacity), _p(cand_count),
                             _stream(stream)), "hs_sum_2d")
+
+
+def hs_sum_interleaved(plan, x, n_bins, n_spectra, norm, snr, harm, drift, cand=None, cand_capacity=0,
+                       cand_count=None, stream=None):
+    _check(load().hs_sum_interleaved(plan, _p(x), int(n_bins), int(n_spectra), _p(norm), _p(snr), _p(harm),
+                                     _p(drift), _p(cand), int(cand_capacity), _p(cand_count), _stream(stream)),
+           "hs_sum_interleaved")
+
+
+def hs_interleave(x, n_bins, n_spectra, elem_bytes, out, stream=None) -> None:
+    _check(load().hs_interleave(_p(x), int(n_bins), int(n_spectra), int(elem_bytes), _p(out), _stream(stream)),
+           "hs_interleave")
 
 
 def hs_get_norm(plan, n, mu_sigma, tables=None, valid=None, stream=None):

@@ -153,6 +153,51 @@ def sum_2d(plane: torch.Tensor, z_min: int, z_max: int, H: int, mode="greedy", *
     return out
 
 
+def interleave(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """[B][N] spectra -> the interleaved layout [N][B] (float32 or 16-bit)."""
+    B, N = x.shape
+    if not x.is_contiguous():
+        raise ValueError("spectra must be contiguous")
+    out = torch.empty((N, B), dtype=x.dtype, device=x.device)
+    hs.hs_interleave(x, N, B, x.element_size(), out, stream)
+    return out
+
+
+def sum_interleaved(x: torch.Tensor, H: int, mode="greedy", threshold=6.0, *, first_bin=1, harmonic_mask=0,
+                    fundamental_end=0, dense=True, candidates=False, capacity=None, norm=None,
+                    plan: hs.Plan | None = None, stream=None, with_norm=False):
+    """Equal-length spectra in the interleaved layout [N][B] (bin-major); outputs [N][B] and/or candidates."""
+    N, B = x.shape
+    if not x.is_contiguous():
+        raise ValueError("the interleaved array must be contiguous")
+    dev = x.device
+    own = plan is None
+    if own:
+        plan = make_plan(H, mode, _dtype_code(x), first_bin=first_bin, harmonic_mask=harmonic_mask,
+                         fundamental_end=fundamental_end, max_spectra=B, threshold=threshold)
+    out = {}
+    snr = harm = drift = cand = count = None
+    if dense:
+        snr = torch.empty((N, B), dtype=torch.float32, device=dev)
+        harm = torch.empty((N, B), dtype=torch.uint8, device=dev)
+        drift = torch.empty((N, B), dtype=torch.uint8, device=dev)
+        out.update(snr=snr, harm=harm, drift=drift)
+    cap = 0
+    if candidates:
+        cap = int(capacity) if capacity is not None else max(1024, x.numel() // 64)
+        cand = torch.empty((max(cap, 1), hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        out.update(cand_raw=cand, count=count)
+    nt = _norm_tensor(norm, B, dev)
+    hs.hs_sum_interleaved(plan.handle, x, N, B, nt, snr, harm, drift, cand, cap, count, stream)
+    if with_norm:
+        out.update(get_norm(plan, B, plan.desc.harmonics, dev, stream))
+    if own:
+        torch.cuda.synchronize(dev)
+        plan.close()
+    return out
+
+
 def quantize_f16(x: torch.Tensor, scale: float, stream=None) -> torch.Tensor:
     """FP16 storage of float32 powers (binary16 patterns viewed as float16)."""
     out = torch.empty(x.numel(), dtype=torch.int16, device=x.device)

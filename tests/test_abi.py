@@ -82,6 +82,17 @@ def test_presto_modes_validation(lib):
     assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_ARG
 
 
+def test_interleave_argument_checks_on_host(lib):
+    # argument checks of the transpose run before anything is enqueued
+    from paper_2202_12817_amd import hs
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.hs_interleave(None, 4, 4, 4, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_interleave(p, 4, 4, 3, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_interleave(p, 4, 4, 4, p, None) == hs.HS_ERR_ARG          # overlap
+    assert lib.hs_interleave(p, 0, 4, 4, p, None) == hs.HS_ERR_ARG
+
+
 def test_masks_must_fit_h(lib):
     from paper_2202_12817_amd import hs
     h = ctypes.c_void_p()

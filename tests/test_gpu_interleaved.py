@@ -1,0 +1,176 @@
+"""GPU parity of the interleaved multi-spectrum layout (Sec. 3.1.1) against the oracle.
+
+Equal-length spectra stored bin-major (x[m B + s]); each column must give
+exactly the oracle's per-spectrum result (Sec. 3.1 Eq. (3), Sec. 3.3 Eq. (5)
+/ Algorithm 2, Eq. (2)): harmonic counts and drifts bit-exact against the
+float mirror, SNR bitwise equal to it and within 1e-5 * max(1, |snr|) of the
+float64 oracle; candidates equal as sorted sets; the transpose bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from gpu_checks import _cands, _np, _same_records, check_dense
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MODES = {"standard": oracle.STANDARD, "greedy": oracle.GREEDY}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_12817_amd import hs
+    hs.load()
+    return torch.device("cuda:0")
+
+
+def _ops():
+    from paper_2202_12817_amd import ops
+    return ops
+
+
+def _spectra(B, N, seed):
+    x, off = synthetic.config3(n_spectra=B, lo=N, hi=N, seed=seed)
+    return x.reshape(B, N)
+
+
+@pytest.mark.parametrize("B,N", [(1, 1), (37, 1000), (130, 4099), (64, 257)])
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_interleave_transpose_bitwise(dev, B, N, dtype):
+    g = np.random.default_rng(B * N)
+    if dtype == "f32":
+        x = g.standard_exponential((B, N)).astype(np.float32)
+        xt = torch.from_numpy(x).to(dev)
+    else:
+        x = g.integers(0, 1 << 15, size=(B, N)).astype(np.int16)
+        xt = torch.from_numpy(x).to(dev)
+    got = _np(_ops().interleave(xt))
+    assert np.array_equal(got, x.T)
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+@pytest.mark.parametrize("f16", [False, True])
+@pytest.mark.parametrize("B,N,H", [(70, 40001, 32), (1, 5000, 13), (64, 2, 4), (65, 3001, 8), (200, 20011, 17)])
+def test_interleaved_dense_and_candidates(dev, mode, f16, B, N, H):
+    X = _spectra(B, N, 80 + B)
+    if f16:
+        X = oracle.quantize_f16(X, np.float32(1.0)).astype(np.float32)
+    xi = np.ascontiguousarray(X.T)
+    xt = torch.from_numpy(xi.astype(np.float16).view(np.int16) if f16 else xi).to(dev)
+    if f16:
+        xt = xt.view(torch.float16)
+    print("interleaved", mode, f16, B, N, H, flush=True)
+    thr = 3.0
+    got = _ops().sum_interleaved(xt, H, mode, thr, dense=True, candidates=True, capacity=X.size, with_norm=True)
+    snr, harm, drift = _np(got["snr"]), _np(got["harm"]), _np(got["drift"])
+    ms = _np(got["mu_sigma"])
+    cands = []
+    for s in range(B):
+        w32 = oracle.hs_1d(X[s], H, MODES[mode])
+        w64 = oracle.hs_1d(X[s], H, MODES[mode], precision="f64")
+        check_dense({"snr": torch.from_numpy(snr[:, s].copy()), "harm": torch.from_numpy(harm[:, s].copy()),
+                     "drift": torch.from_numpy(drift[:, s].copy())}, w32, w64, "spectrum %d" % s)
+        assert (ms[s, 0], ms[s, 1]) == (w32["mu1"], w32["sigma1"]) or not np.isfinite(w32["sigma1"])
+        cands.append(oracle.candidates(w32["snr"], w32["harm"], w32["drift"], thr, spectrum=s))
+    want = np.concatenate(cands)
+    recs, n = _cands(got)
+    assert n == want.size
+    assert _same_records(recs, want)
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+def test_interleaved_equals_batched(dev, mode):
+    B, N = 96, 65536
+    X = _spectra(B, N, 83)
+    xn = torch.from_numpy(X.reshape(-1)).to(dev)
+    off = torch.from_numpy(np.arange(B + 1, dtype=np.int64) * N).to(dev)
+    a = _ops().sum_batched(xn, off, 32, mode, 6.0, dense=True, candidates=True, capacity=1 << 20)
+    b = _ops().sum_interleaved(_ops().interleave(xn.view(B, N)), 32, mode, 6.0, dense=True, candidates=True,
+                               capacity=1 << 20)
+    for k in ("snr", "harm", "drift"):
+        assert torch.equal(a[k].view(B, N).t(), b[k]), k
+    ra, na = _cands(a)
+    rb, nb = _cands(b)
+    assert na == nb and _same_records(ra, rb)
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+def test_interleaved_options_and_norm(dev, mode):
+    B, N = 66, 30011
+    X = _spectra(B, N, 84)
+    X[5] = 2.5                                   # a degenerate spectrum: all outputs zero
+    xt = torch.from_numpy(np.ascontiguousarray(X.T)).to(dev)
+    cases = [dict(first_bin=7), dict(fundamental_end=5000), dict(harmonic_mask=0b1010),
+             dict(harmonic_mask=1 << 31), dict(first_bin=3, fundamental_end=20000)]
+    for c in cases:
+        print("interleaved options", mode, c, flush=True)
+        got = _ops().sum_interleaved(xt, 32, mode, dense=True, **c)
+        snr, harm, drift = _np(got["snr"]), _np(got["harm"]), _np(got["drift"])
+        for s in (0, 5, 17, 65):
+            w32 = oracle.hs_1d(X[s], 32, MODES[mode], **c)
+            check_dense({"snr": torch.from_numpy(snr[:, s].copy()), "harm": torch.from_numpy(harm[:, s].copy()),
+                         "drift": torch.from_numpy(drift[:, s].copy())}, w32, None, "%s s=%d" % (c, s))
+        assert not harm[:, 5].any() and not snr[:, 5].any()
+    norm = np.tile([1.25, 0.75], B)
+    got = _ops().sum_interleaved(xt, 16, mode, dense=True, norm=norm)
+    for s in (0, 33):
+        w32 = oracle.hs_1d(X[s], 16, MODES[mode], norm=(1.25, 0.75))
+        check_dense({"snr": torch.from_numpy(_np(got["snr"])[:, s].copy()),
+                     "harm": torch.from_numpy(_np(got["harm"])[:, s].copy()),
+                     "drift": torch.from_numpy(_np(got["drift"])[:, s].copy())}, w32, None, "norm s=%d" % s)
+
+
+def test_interleaved_argument_checks(dev):
+    from paper_2202_12817_amd import hs
+    plan = _ops().make_plan(8, "presto")
+    x = torch.ones((100, 4), dtype=torch.float32, device=dev)
+    snr = torch.empty((100, 4), dtype=torch.float32, device=dev)
+    harm = torch.empty((100, 4), dtype=torch.uint8, device=dev)
+    try:
+        with pytest.raises(hs.HsError) as e:
+            hs.hs_sum_interleaved(plan.handle, x, 100, 4, None, snr, harm, None)
+        assert e.value.status == hs.HS_ERR_UNSUPPORTED
+    finally:
+        plan.close()
+    plan = _ops().make_plan(8, "greedy", max_spectra=4)
+    try:
+        with pytest.raises(hs.HsError) as e:
+            hs.hs_sum_interleaved(plan.handle, x, 1 << 29, 4, None, snr, harm, None)    # 2^31 elements
+        assert e.value.status == hs.HS_ERR_ARG
+        with pytest.raises(hs.HsError) as e:
+            hs.hs_sum_interleaved(plan.handle, x, 100, 5, None, snr, harm, None)        # above max_spectra
+        assert e.value.status == hs.HS_ERR_ARG
+    finally:
+        plan.close()
+    with pytest.raises(hs.HsError):
+        hs.hs_interleave(x, 100, 4, 3, snr)                                          # element size
+    with pytest.raises(hs.HsError):
+        hs.hs_interleave(x, 100, 4, 4, x)                                            # in place
+
+
+@pytest.mark.parametrize("mode", ["standard", "greedy"])
+def test_table2_workload_interleaved_sampled(dev, mode):
+    """The Table 2 shape (1024 spectra of 2^17 bins, H = 32) interleaved, in the
+    launch the benchmark times: dense outputs and SNR > 6 candidates on sampled
+    spectra against the oracle."""
+    x, off = synthetic.table2()
+    B, N = off.size - 1, int(off[1])
+    xn = torch.from_numpy(x).to(dev)
+    xi = _ops().interleave(xn.view(B, N))
+    del xn
+    print("table2 interleaved", mode, flush=True)
+    got = _ops().sum_interleaved(xi, 32, mode, 6.0, dense=True, candidates=True, capacity=1 << 22)
+    recs, n = _cands(got)
+    assert n == recs.size
+    X = x.reshape(B, N)
+    for s in (0, 63, 64, 511, 1023):
+        w32 = oracle.hs_1d(X[s], 32, MODES[mode])
+        col = {k: got[k][:, s].contiguous().cpu() for k in ("snr", "harm", "drift")}
+        check_dense(col, w32, None, "%s spectrum %d" % (mode, s))
+        wc = oracle.candidates(w32["snr"], w32["harm"], w32["drift"], 6.0, spectrum=s)
+        assert _same_records(recs[recs["spectrum"] == s], wc), s
+    del xi, got
