@@ -272,8 +272,55 @@ def table2_leg(hs, torch, dev, steps, warmup):
                 r["ratio_to_paper_v100"] = r["gbin_s"] / paper
             res["H%d" % h] = r
         out[mname] = res
+    out["interleaved"] = interleaved_leg(hs, torch, xt, ot, B, n_bins // B, snr, harm, steps, warmup, stream)
     del xt, snr, harm
     return out
+
+
+def _timed_sum(hs, torch, plan, call, steps, warmup):
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    hs.hs_plan_set_timing(plan.handle, True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    c, nm, sm = hs.hs_plan_get_timing(plan.handle)
+    hs.hs_plan_set_timing(plan.handle, False)
+    return sm / max(1, c), nm / max(1, c)
+
+
+def interleaved_leg(hs, torch, xt, ot, B, N, snr, harm, steps, warmup, stream):
+    """The same spectra in the interleaved layout of Sec. 3.1.1 (bin-major, one
+    lane per spectrum) against the natural layout, simple and greedy sums, dense
+    snr/harm: harmonic-sum kernel time of each, and the transpose that builds
+    the layout (HIP events)."""
+    xi = torch.empty((N, B), dtype=torch.float32, device=xt.device)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hs.hs_interleave(xt, N, B, 4, xi, stream)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        hs.hs_interleave(xt, N, B, 4, xi, stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    res = {"transpose_ms": t0.elapsed_time(t1) / steps,
+           "note": "sum-kernel ms per call; natural = hs_sum_batched (tuned launch), interleaved = hs_sum_interleaved"}
+    for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
+        r = {}
+        for h in (4, 8, 16, 32):
+            plan = hs.Plan(harmonics=h, mode=mode, dtype=hs.HS_F32, max_spectra=B)
+            hs.hs_plan_tune_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, None, stream)
+            nat, _ = _timed_sum(hs, torch, plan, lambda: hs.hs_sum_batched(
+                plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, stream), steps, warmup)
+            il, il_norm = _timed_sum(hs, torch, plan, lambda: hs.hs_sum_interleaved(
+                plan.handle, xi, N, B, None, snr, harm, None, None, 0, None, stream), steps, warmup)
+            plan.close()
+            r["H%d" % h] = {"natural_sum_ms": nat, "interleaved_sum_ms": il, "interleaved_norm_ms": il_norm,
+                            "gbin_s_interleaved": N * B / (il * 1e-3) / 1e9, "speedup": nat / il}
+        res[mname] = r
+    del xi
+    return res
 
 
 def small_1d_leg(hs, torch, dev):

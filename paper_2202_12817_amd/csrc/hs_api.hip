@@ -336,6 +336,8 @@ hs_status enqueue_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t
     sa.chunks = hs::kChunksBatched;
     sa.user_norm = norm;
     sa.il_spectra = n_spectra;
+    sa.tab_t = p->tab_t;
+    sa.tab_stride = p->max_groups;
     hs_status s = run_norm(p, sa, n_spectra, st);
     if (s != HS_OK) return s;
     hs::IlArgs a{};
@@ -343,6 +345,8 @@ hs_status enqueue_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t
     a.n_bins = n_bins;
     a.n_spectra = n_spectra;
     a.norm = p->norm;
+    a.tab_t = p->tab_t;
+    a.tab_stride = p->max_groups;
     a.first_bin = p->desc.first_bin;
     a.H = p->desc.harmonics;
     a.n_end = n_end_of(p->desc, n_bins);
@@ -647,7 +651,7 @@ hs_status check_desc(const hs_plan_desc &d) {
 // Device workspace of a plan: one block, pieces at 256-byte aligned offsets.
 struct Layout {
     int parts_cap;
-    size_t norm, parts, tickets, prefix, ray, total;
+    size_t norm, parts, tickets, prefix, ray, tab_t, total;
 };
 
 constexpr size_t kWsAlign = 256;
@@ -671,6 +675,8 @@ Layout layout(const hs_plan_desc &d) {
     o = align_up(o + sizeof(uint32_t) * ((size_t)d.max_spectra + 1));
     l.ray = o;
     o = align_up(o + sizeof(hs::RayBand) * hs::kRayMaxBands);
+    l.tab_t = o;
+    o = align_up(o + sizeof(float2) * HS_MAX_HARMONICS * (size_t)d.max_spectra);
     l.total = o;
     return l;
 }
@@ -716,6 +722,7 @@ hs_status create_plan(const hs_plan_desc *desc, void *workspace, size_t bytes, h
     p->tickets = (uint32_t *)(p->ws + l.tickets);
     p->prefix = (uint32_t *)(p->ws + l.prefix);
     p->ray = (hs::RayBand *)(p->ws + l.ray);
+    p->tab_t = (float2 *)(p->ws + l.tab_t);
     hs_status ss = setup_xcd(p);
     if (ss != HS_OK) {
         hs_plan_destroy(p);

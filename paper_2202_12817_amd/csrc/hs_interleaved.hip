@@ -13,8 +13,9 @@
 //   * the greedy drift is per spectrum, so the greedy pair sits at rows
 //     k n + d_s and k n + d_s + 1 (a per-lane row offset added to the scalar
 //     one); lanes with the same drift share cache lines;
-//   * each lane keeps its spectrum's (rs_k, nm_k) table in registers for the
-//     whole tile of fundamentals it walks;
+//   * the lanes read their spectra's (rs_k, nm_k) from a copy of the tables
+//     stored spectrum-fastest (one coalesced 64-entry row per harmonic,
+//     shared by the fundamentals walked together);
 //   * the number of harmonics K(n) = min(H, (N-1) / (n + greedy)) is the same
 //     for every lane and only falls as n grows: it is walked down per
 //     fundamental instead of divided.
@@ -76,6 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_stats_il(StatsArgs a) {
 }
 
 constexpr int kIlStage = 64;   // candidate records staged per wave
+// fundamentals walked together by a wave: their loads (and the greedy
+// dependency chains) overlap
+template <bool GREEDY>
+constexpr int il_chains() { return GREEDY ? 4 : 4; }
 
 // One wave task: spectra group g (lanes = spectra 64 g .. 64 g + 63) x
 // fundamentals [n_lo, n_lo + tile).  Workgroup L (renumbered as in
@@ -83,6 +88,7 @@ constexpr int kIlStage = 64;   // candidate records staged per wave
 template <int HMAX, bool GREEDY, bool F16>
 __global__ __launch_bounds__(kBlock) void k_sum_il(IlArgs a) {
     constexpr uint32_t eb = F16 ? 2u : 4u;
+    constexpr int kIlChains = il_chains<GREEDY>();
     __shared__ hs_candidate s_stage[kBlock / 64][kIlStage];
     Stage st{s_stage[threadIdx.x >> 6], 0};
     int bx, by;
@@ -97,20 +103,14 @@ __global__ __launch_bounds__(kBlock) void k_sum_il(IlArgs a) {
     const int B = a.n_spectra;
     const int s = g * 64 + lane;
     const bool live = s < B;
-    const NormRec *nr = a.norm + (live ? s : 0);
-    const int valid = live ? nr->valid : 0;
-    float rs[HMAX], nm[HMAX];
-#pragma unroll
-    for (int k = 0; k < HMAX; ++k) {
-        const float2 t = nr->t[k];
-        rs[k] = t.x;
-        nm[k] = t.y;
-    }
+    const int sc = live ? s : B - 1;
+    const int valid = live ? a.norm[sc].valid : 0;
+    const float2 *tab = a.tab_t + sc;           // (rs_k, nm_k) at tab[(k-1) tab_stride]: one coalesced row per k
     const uint32_t rb = (uint32_t)B * eb;                       // bytes per row (bin)
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(a.x, (uint32_t)(N * B * eb));
     // lanes past the last spectrum read the last spectrum's column (never
     // written out), so every address stays inside the array
-    const uint32_t vlane = (uint32_t)(live ? s : B - 1) * eb;
+    const uint32_t vlane = (uint32_t)sc * eb;
     const int64_t n_end = a.n_end < N ? a.n_end : N;
     const int64_t gr = GREEDY ? 1 : 0;
     int K = a.H;
@@ -119,58 +119,88 @@ __global__ __launch_bounds__(kBlock) void k_sum_il(IlArgs a) {
         const int64_t kk = (N - 1) / (n0 + gr);
         if (kk < K) K = (int)kk;
     }
-    for (int64_t n = n_lo; n < n_hi; ++n) {
-        int Kn = 0;
-        if (n >= a.first_bin && n < n_end) {
-            while (K > 0 && (int64_t)K * (n + gr) > N - 1) --K;     // K(n), wave-uniform
-            Kn = K;
+    // kIlChains consecutive fundamentals walk together, so their loads (and
+    // the greedy dependency chains) overlap; K is the same for every lane
+    for (int64_t n0 = n_lo; n0 < n_hi; n0 += kIlChains) {
+        int Kn[kIlChains];
+        float S[kIlChains], best[kIlChains];
+        int kb[kIlChains], db[kIlChains], d[kIlChains];
+        uint32_t dv[kIlChains], step[kIlChains], srow[kIlChains];
+#pragma unroll
+        for (int j = 0; j < kIlChains; ++j) {
+            const int64_t n = n0 + j;
+            Kn[j] = 0;
+            if (n < n_hi && n >= a.first_bin && n < n_end) {
+                while (K > 0 && (int64_t)K * (n + gr) > N - 1) --K;     // K(n), wave-uniform
+                Kn[j] = K;
+            }
+            S[j] = 0.0f;
+            best[j] = 0.0f;
+            kb[j] = db[j] = d[j] = 0;
+            dv[j] = 0;                                  // d rb
+            step[j] = (uint32_t)(n < n_hi ? n : 0) * rb;   // n rb < N B eb < 2^32
+            srow[j] = 0;
         }
-        float S = 0.0f, best = 0.0f;
-        int kb = 0, db = 0, d = 0;
-        uint32_t dv = 0;                            // d rb
-        const uint32_t step = (uint32_t)n * rb;     // n rb < N B eb < 2^32
-        uint32_t srow = 0;
+        int Kmax = 0;                                   // chains below first_bin or past the end have K = 0
+#pragma unroll
+        for (int j = 0; j < kIlChains; ++j) Kmax = Kn[j] > Kmax ? Kn[j] : Kmax;
 #pragma unroll
         for (int k = 1; k <= HMAX; ++k) {
-            if (k > Kn) break;                      // wave-uniform
-            srow += step;                           // row k n, scalar
-            float v;
-            if constexpr (GREEDY) {
-                const float x0 = load_off<F16>(rsrc, vlane + dv, srow);
-                const float x1 = load_off<F16>(rsrc, vlane + dv, srow + rb);
-                const bool up = x1 > x0;
-                v = up ? x1 : x0;
-                dv += up ? rb : 0u;
-                d += up ? 1 : 0;
-            } else {
-                v = load_off<F16>(rsrc, vlane, srow);
+            if (k > Kmax) break;                        // wave-uniform
+            float v[kIlChains];
+#pragma unroll
+            for (int j = 0; j < kIlChains; ++j) {
+                srow[j] += step[j];                     // row k n, scalar
+                if (k <= Kn[j]) {                       // wave-uniform
+                    if constexpr (GREEDY) {
+                        const float x0 = load_off<F16>(rsrc, vlane + dv[j], srow[j]);
+                        const float x1 = load_off<F16>(rsrc, vlane + dv[j], srow[j] + rb);
+                        const bool up = x1 > x0;
+                        v[j] = up ? x1 : x0;
+                        dv[j] += up ? rb : 0u;
+                        d[j] += up ? 1 : 0;
+                    } else {
+                        v[j] = load_off<F16>(rsrc, vlane, srow[j]);
+                    }
+                }
             }
-            S = S + v;
-            const float snr = __builtin_fmaf(S, rs[k - 1], nm[k - 1]);
-            if ((a.kmask >> (k - 1)) & 1ull) {
-                if (kb == 0 || snr > best) {
-                    best = snr;
-                    kb = k;
-                    db = d;
+            const float2 t = tab[(int64_t)(k - 1) * a.tab_stride];
+#pragma unroll
+            for (int j = 0; j < kIlChains; ++j) {
+                if (k <= Kn[j]) {
+                    S[j] = S[j] + v[j];
+                    const float snr = __builtin_fmaf(S[j], t.x, t.y);
+                    if ((a.kmask >> (k - 1)) & 1ull) {
+                        if (kb[j] == 0 || snr > best[j]) {
+                            best[j] = snr;
+                            kb[j] = k;
+                            db[j] = d[j];
+                        }
+                    }
                 }
             }
         }
-        if (!valid) kb = 0;
-        const float o_snr = kb ? best : 0.0f;
-        const int64_t o = n * B + s;
-        if (live) {
-            if (a.snr) a.snr[o] = o_snr;
-            if (a.harm) a.harm[o] = (uint8_t)kb;
-            if (a.drift) a.drift[o] = (uint8_t)(kb ? db : 0);
-        }
-        if (a.cand) {
-            hs_candidate rec;
-            rec.spectrum = (uint32_t)s;
-            rec.bin = (uint32_t)n;
-            rec.snr = o_snr;
-            rec.harm = (uint16_t)kb;
-            rec.drift = (uint16_t)(kb ? db : 0);
-            stage_push<kIlStage>(st, a.cand, a.cap, a.count, live && kb > 0 && o_snr > a.thr, rec);
+#pragma unroll
+        for (int j = 0; j < kIlChains; ++j) {
+            const int64_t n = n0 + j;
+            if (n >= n_hi) continue;                    // wave-uniform
+            const int kbj = valid ? kb[j] : 0;
+            const float o_snr = kbj ? best[j] : 0.0f;
+            const int64_t o = n * B + s;
+            if (live) {
+                if (a.snr) a.snr[o] = o_snr;
+                if (a.harm) a.harm[o] = (uint8_t)kbj;
+                if (a.drift) a.drift[o] = (uint8_t)(kbj ? db[j] : 0);
+            }
+            if (a.cand) {
+                hs_candidate rec;
+                rec.spectrum = (uint32_t)s;
+                rec.bin = (uint32_t)n;
+                rec.snr = o_snr;
+                rec.harm = (uint16_t)kbj;
+                rec.drift = (uint16_t)(kbj ? db[j] : 0);
+                stage_push<kIlStage>(st, a.cand, a.cap, a.count, live && kbj > 0 && o_snr > a.thr, rec);
+            }
         }
     }
     if (a.cand) stage_flush(st, a.cand, a.cap, a.count);

@@ -35,6 +35,8 @@ struct StatsArgs {
     NormRec *norm;            // [groups]
     const double *user_norm;  // NULL or [2 groups] (mu1, sigma1)
     int32_t il_spectra;       // interleaved layout: spectra per row (group g = spectrum g of n_bins bins)
+    float2 *tab_t;            // NULL, or also write (rs_k, nm_k) of group g to tab_t[(k-1) tab_stride + g]
+    int32_t tab_stride;
 };
 
 // Harmonic sum over 1D spectra (one, or a batch through `offsets`).
@@ -102,6 +104,8 @@ struct IlArgs {
     int64_t n_bins;
     int32_t n_spectra;
     const NormRec *norm;      // [n_spectra]
+    const float2 *tab_t;      // (rs_k, nm_k) of spectrum s at tab_t[(k-1) tab_stride + s]
+    int32_t tab_stride;
     int32_t first_bin;
     int32_t H;
     int64_t n_end;
@@ -247,6 +251,7 @@ struct hs_plan {
     uint32_t *tickets;           // device [kMaxXcd] work-queue counters of the persistent kernel
     uint32_t *prefix;            // device [max_groups + 1] chunk prefix of the persistent kernel
     hs::RayBand *ray;            // device [kRayMaxBands] band table of the ray-tiled plane kernel
+    float2 *tab_t;               // device [HS_MAX_HARMONICS][max_groups] tables, spectrum fastest (interleaved walk)
     int n_cu, n_xcd;             // device shape
     int xcd_f;                   // fundamentals per lane of the batched kernel
     int xcd_blocks;              // persistent grid of the batched kernel

@@ -205,6 +205,7 @@ __global__ __launch_bounds__(64) void k_finalize(StatsArgs a) {
             nm = (float)(-(mu_k / sig_k));
         }
         rec->t[lane] = make_float2(rs, nm);
+        if (a.tab_t) a.tab_t[(int64_t)lane * a.tab_stride + g] = make_float2(rs, nm);
     }
 }
 
