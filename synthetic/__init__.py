@@ -32,6 +32,7 @@ __all__ = [
     "rng", "exp_noise", "gaussian_weights", "train_amplitude", "inject_train",
     "random_trains", "config1", "config2", "config3_lengths", "config3_spectrum",
     "config3", "config4", "inject_track", "random_tracks", "table2",
+    "von_mises_kappa", "von_mises_series", "power_spectrum",
 ]
 
 
@@ -199,3 +200,37 @@ def table2(n_spectra: int = 1024, length: int = 131072, seed: int = 5, threads: 
     spectra of 2^17 bins each): noise and trains drawn as for the batched
     workload, every spectrum ``length`` bins.  Returns (x, offsets)."""
     return config3(n_spectra=n_spectra, lo=length, hi=length, seed=seed, threads=threads)
+
+
+def von_mises_kappa(duty: float) -> float:
+    """Shape parameter of the modified von Mises pulse whose full width at half
+    maximum is ``duty`` of the period: the half-maximum phase theta solves
+    exp(kappa (cos theta - 1)) = 1/2 with theta = pi duty."""
+    return math.log(2.0) / (1.0 - math.cos(math.pi * duty))
+
+
+def von_mises_series(f_r: float, T: float = 20.0, ts: float = 64e-6, duty: float = 0.04, amp: float = 1.0,
+                     phase: float = 0.0) -> np.ndarray:
+    """Noise-free pulsar time series from the modified von Mises profile of
+    Sec. 4.1 (float64): amp (exp(kappa cos(2 pi f_r t + phase)) - exp(-kappa))
+    / (I0(kappa) - exp(-kappa)) at t = 0, ts, ..., the profile's mean removed
+    is not done here (the DC bin is excluded from the sums anyway)."""
+    kappa = von_mises_kappa(duty)
+    n = int(round(T / ts))
+    t = np.arange(n, dtype=np.float64) * ts
+    # exp(kappa cos x) / I0(kappa) evaluated as exp(kappa (cos x - 1)) / (I0(kappa) e^-kappa) for large kappa
+    i0e = float(np.i0(kappa)) * math.exp(-kappa) if kappa < 700 else 1.0 / math.sqrt(2.0 * math.pi * kappa)
+    num = np.exp(kappa * (np.cos(2.0 * np.pi * f_r * t + phase) - 1.0)) - math.exp(-2.0 * kappa)
+    return amp * num / (i0e - math.exp(-2.0 * kappa))
+
+
+def power_spectrum(series: np.ndarray, noise_sigma: float = 1.0, seed: int | None = None) -> np.ndarray:
+    """Power spectrum |FFT|^2 / (N sigma^2) of a real series, float32 (bins
+    0..N/2), normalised so that white noise of standard deviation ``noise_sigma``
+    per sample has unit mean power; with ``seed`` that noise is added to the
+    series first."""
+    x = np.asarray(series, dtype=np.float64)
+    if seed is not None:
+        x = x + rng(seed, 7).normal(0.0, noise_sigma, size=x.size)
+    X = np.fft.rfft(x)
+    return ((X.real ** 2 + X.imag ** 2) / (x.size * noise_sigma ** 2)).astype(np.float32)
