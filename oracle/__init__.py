@@ -26,6 +26,9 @@ What it computes, in the paper's order:
    Sec. 3.2 (Eq. (4), Algorithm 1: PRESTO, PRESTO_all, PRESTO+) are indexed by
    the last bin of the series: stage K sums the bins nearest to ``h n / K``.
 4. Candidates: every bin whose best SNR is strictly above a threshold.
+5. The pipeline's neighbours: the power spectrum of complex FFT bins with
+   optional inter-binning (the step before the sum, Sec. 2), and peak
+   clustering of the candidates (the step after it).
 
 Precision ``"f32"`` mirrors the precision of the GPU's decisions (float sums
 in harmonic order, fused float SNR) for bit-exact comparison of harmonic
@@ -45,6 +48,7 @@ __all__ = [
     "build", "exact_sums", "stats", "norm_from_data", "tables", "is_degenerate",
     "keff", "hs_1d", "hs_2d", "hs_batched", "candidates", "quantize_f16",
     "GREEDY", "STANDARD", "PRESTO", "PRESTO_ALL", "PRESTO_PLUS", "presto_stages",
+    "power_spectrum", "cluster_peaks", "INTERBIN_FACTOR",
 ]
 
 STANDARD = 0
@@ -370,3 +374,69 @@ def quantize_f16(x, scale):
     """
     q = np.asarray(x, dtype=np.float32) / np.float32(scale)
     return np.clip(q, np.float32(-65504.0), np.float32(65504.0)).astype(np.float16)
+
+
+# ---------------------------------------------------------------------------
+# 5. pipeline neighbours: power spectrum with inter-binning, peak clustering
+# ---------------------------------------------------------------------------
+
+INTERBIN_FACTOR = np.float32((math.pi * math.pi) / 16.0)    # (pi/4)^2, rounded once to float
+
+
+def power_spectrum(fft, interbin=False, scale=1.0):
+    """Powers of complex FFT bins ``fft`` (complex64, N bins), float32.
+
+    The harmonic sum runs on a power spectrum, possibly inter-binned (Sec. 2;
+    the paper cites Ransom et al. 2002 for the step).  Integer bin m:
+    ``scale * (re^2 + im^2)``; with ``interbin`` the N - 1 half bins between m
+    and m + 1 are added, interleaved (output 2N - 1 values, bin 2m = bin m,
+    bin 2m + 1 = half bin m + 1/2): the half-bin amplitude of a
+    rectangular-window DFT is estimated as (pi/4)(F_m - F_{m+1}), so its power
+    is ``(scale (pi/4)^2) |F_m - F_{m+1}|^2``.  Every operation is one float32
+    rounding in the order written: ``p = re*re + im*im`` (two products, one
+    sum), then one product with the float factor.
+    """
+    F = np.ascontiguousarray(fft, dtype=np.complex64)
+    re, im = F.real.astype(np.float32), F.imag.astype(np.float32)
+    sc = np.float32(scale)
+    p = (re * re + im * im) * sc
+    if not interbin:
+        return p
+    dr = re[:-1] - re[1:]
+    di = im[:-1] - im[1:]
+    fh = np.float32(float(scale) * float(INTERBIN_FACTOR))      # scale (pi/4)^2, one rounding from float64
+    h = (dr * dr + di * di) * fh
+    out = np.empty(2 * F.size - 1, dtype=np.float32)
+    out[0::2] = p
+    out[1::2] = h
+    return out
+
+
+def cluster_peaks(snr, harm, drift, threshold, radius, offsets=None):
+    """Candidates that are peaks: ``snr > threshold`` (float32, strict), at
+    least one harmonic summed, and no bin of the same spectrum within
+    ``radius`` bins beats it (a larger SNR, or an equal SNR at a lower bin).
+    Returns CANDIDATE_DTYPE records sorted by (spectrum, bin); ``offsets``
+    (CSR) splits the dense arrays into spectra (None: one spectrum)."""
+    snr = np.asarray(snr, dtype=np.float32)
+    harm = np.asarray(harm)
+    drift = np.asarray(drift)
+    off = np.array([0, snr.size], dtype=np.int64) if offsets is None else np.asarray(offsets, dtype=np.int64)
+    recs = []
+    for s in range(off.size - 1):
+        lo, hi = int(off[s]), int(off[s + 1])
+        for n in range(lo, hi):
+            v = snr[n]
+            if not (v > np.float32(threshold)) or harm[n] == 0:
+                continue
+            keep = True
+            for j in range(max(lo, n - radius), min(hi, n + radius + 1)):
+                if j != n and (snr[j] > v or (snr[j] == v and j < n)):
+                    keep = False
+                    break
+            if keep:
+                recs.append((s, n - lo, v, int(harm[n]), int(drift[n])))
+    out = np.zeros(len(recs), dtype=CANDIDATE_DTYPE)
+    for i, r in enumerate(recs):
+        out[i] = r
+    return out

@@ -82,3 +82,26 @@ def read_presto(name="hand_presto.txt"):
                                   first=int(kv["first"]), n=int(kv["n"]), stages=stages,
                                   harm=int(kv["harm"])))
     return spectra, cases, lastbins
+
+
+def read_peaks(name="hand_peaks.txt"):
+    """Offsets, dense snr / harm and the clustering cases of the peak fixture."""
+    off = snr = harm = None
+    cases = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "spectra":
+                off = np.array(_ints(tok[1]), dtype=np.int64)
+            elif tok[0] == "snr":
+                snr = np.array([float(v) for v in tok[1:]], dtype=np.float32)
+            elif tok[0] == "harm":
+                harm = np.array([int(v) for v in tok[1:]], dtype=np.uint8)
+            elif tok[0] == "case":
+                kv = _kv(tok[1:])
+                keep = [tuple(int(v) for v in p.split(":")) for p in kv["keep"].split(",") if p]
+                cases.append(dict(threshold=float(kv["threshold"]), radius=int(kv["radius"]), keep=keep))
+    return off, snr, harm, cases

@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hs_oracle.c")
 PINS = ["tests/test_oracle_golden.py", "tests/test_oracle_stats.py", "tests/test_oracle_bruteforce.py",
-        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py", "tests/test_oracle_presto.py"]
+        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py", "tests/test_oracle_presto.py",
+        "tests/test_oracle_pipeline.py"]
 
 C_MUTANTS = {
     "greedy-tie-moves": ("if (b > a) { d += 1; v = b; }", "if (b >= a) { d += 1; v = b; }"),
@@ -48,6 +49,14 @@ PY_MUTANTS = {
     "    k = np.arange(1, H + 1)\n"
     "    return mu, sig * np.sqrt(k), (1.0 / (sig * np.sqrt(k))).astype(np.float32), (-(mu / (sig * np.sqrt(k)))).astype(np.float32)\n"
     "oracle.tables = tables\n",
+    "interbin-amplitude-not-squared": "import oracle, math, numpy as np\n"
+    "oracle.INTERBIN_FACTOR = np.float32(math.pi / 4)\n",
+    "peak-tie-to-higher-bin": "import oracle, inspect\n"
+    "src = inspect.getsource(oracle.cluster_peaks).replace('and j < n', 'and j > n')\n"
+    "exec(src, oracle.__dict__)\n",
+    "peak-window-one-sided": "import oracle, inspect\n"
+    "src = inspect.getsource(oracle.cluster_peaks).replace('min(hi, n + radius + 1)', 'n + 1')\n"
+    "exec(src, oracle.__dict__)\n",
     "variance-about-zero": "import oracle\n"
     "_s = oracle.stats\n"
     "def stats(x, first_bin=1):\n"
