@@ -237,6 +237,39 @@ hs_status hs_interleave(const void *x, int64_t n_bins, int32_t n_spectra, int32_
                         void *out, void *stream);
 
 /*
+ * The power spectrum the sum runs on, from complex FFT bins (the step before
+ * the harmonic sum; Sec. 2 names power-spectrum calculation with
+ * inter-binning).  fft: n_bins complex values (float re, float im pairs,
+ * 8-byte aligned).  interbin 0: out[m] = fl(fl(fl(re*re) + fl(im*im)) * scale),
+ * n_bins floats.  interbin 1: 2 n_bins - 1 floats, out[2m] = bin m as above
+ * and out[2m+1] = the half bin between m and m + 1, whose amplitude is
+ * estimated as (pi/4)(F_m - F_{m+1}):  fl(fl(fl(dr*dr) + fl(di*di)) * s_h)
+ * with dr, di the float differences and s_h = fl32(scale * fl32(pi^2/16)).
+ * scale > 0 (e.g. 1 / (N sigma^2) for unit mean noise power); 1 <= n_bins < 2^31;
+ * fft and out must not overlap.  Stream-ordered; no plan needed.
+ */
+hs_status hs_power_spectrum(const void *fft, int64_t n_bins, int32_t interbin, float scale, float *out,
+                            void *stream);
+
+/*
+ * Peak clustering of dense outputs (the step after the sum): a candidate
+ * (snr > threshold, strict float compare, harm > 0) is kept if no bin of the
+ * same spectrum within radius bins beats it -- a larger snr, or an equal snr
+ * at a lower bin -- so kept peaks are more than radius bins apart.
+ *   snr, harm, drift   dense outputs of a sum call (drift may be NULL: 0);
+ *   offsets            NULL: one spectrum of n_bins (n_spectra = 1); else
+ *                      [n_spectra + 1] device offsets as for hs_sum_batched
+ *                      (n_bins = total bins, 1 <= n_spectra <= 65535);
+ *   cand/cand_capacity/cand_count   as for hs_sum_batched (bin = bin within
+ *                      its spectrum; *cand_count zeroed by the call).
+ * radius >= 0 (0: every candidate).  Stream-ordered; no plan needed.
+ */
+hs_status hs_cluster_peaks(const float *snr, const uint8_t *harm, const uint8_t *drift, const int64_t *offsets,
+                           int64_t n_bins, int32_t n_spectra, int32_t radius, float threshold,
+                           hs_candidate *cand, int64_t cand_capacity, unsigned long long *cand_count,
+                           void *stream);
+
+/*
  * Export the normalisation used by the most recent sum call on this plan
  * (stream-ordered device-to-device copy of its first n entries).
  *   mu_sigma  [2 n] doubles (mu1, sigma1); tables NULL or [n][2][H] floats

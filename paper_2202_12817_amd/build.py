@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhs.so")
-SOURCES = ["hs_api.hip", "hs_stats.hip", "hs_sum.hip", "hs_sum_xcd.hip", "hs_sum_2d_ray.hip", "hs_presto.hip", "hs_interleaved.hip"]
+SOURCES = ["hs_api.hip", "hs_stats.hip", "hs_sum.hip", "hs_sum_xcd.hip", "hs_sum_2d_ray.hip", "hs_presto.hip", "hs_interleaved.hip", "hs_pipeline.hip"]
 
 # -ffp-contract=off: every float operation is the single rounding written in
 # the source (the SNR's fma is explicit).  Packed FP32 instructions are

@@ -1,6 +1,7 @@
 // C ABI of the harmonic-sum library: argument validation, plan/workspace
 // management and the launch sequence of every entry point (declared and
 // documented in include/hs.h).
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -873,6 +874,51 @@ hs_status hs_interleave(const void *x, int64_t n_bins, int32_t n_spectra, int32_
     if (xb < ob + bytes && ob < xb + bytes) return fail(HS_ERR_ARG, "x and out overlap");
     hipError_t e = hs::launch_interleave(x, n_bins, n_spectra, elem_bytes, out, (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "interleave kernel");
+    return HS_OK;
+}
+
+hs_status hs_power_spectrum(const void *fft, int64_t n_bins, int32_t interbin, float scale, float *out, void *stream) {
+    if (!fft || !out) return fail(HS_ERR_ARG, "null argument");
+    if (n_bins < 1 || n_bins >= (1ll << 31)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^31)");
+    if (((uintptr_t)fft & 7u) || ((uintptr_t)out & 3u)) return fail(HS_ERR_ARG, "misaligned buffer");
+    if (!(scale > 0.0f) || !(scale < __builtin_inff())) return fail(HS_ERR_ARG, "scale must be positive and finite");
+    const int64_t out_n = interbin ? 2 * n_bins - 1 : n_bins;
+    const char *a = (const char *)fft, *b = (const char *)out;
+    if (a < b + 4 * out_n && b < a + 8 * n_bins) return fail(HS_ERR_ARG, "fft and out overlap");
+    // scale (pi/4)^2: the float factor rounded once, times scale in double, rounded once
+    const float f16 = (float)((M_PI * M_PI) / 16.0);
+    const float sch = (float)((double)scale * (double)f16);
+    hipError_t e = hs::launch_power(fft, n_bins, interbin != 0, scale, sch, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "power-spectrum kernel");
+    return HS_OK;
+}
+
+hs_status hs_cluster_peaks(const float *snr, const uint8_t *harm, const uint8_t *drift, const int64_t *offsets,
+                           int64_t n_bins, int32_t n_spectra, int32_t radius, float threshold, hs_candidate *cand,
+                           int64_t cand_capacity, unsigned long long *cand_count, void *stream) {
+    if (!snr || !harm || !cand_count || (!cand && cand_capacity > 0)) return fail(HS_ERR_ARG, "null argument");
+    if (cand_capacity < 0) return fail(HS_ERR_ARG, "negative capacity");
+    if (n_bins < 1 || n_bins >= (1ll << 32)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^32)");
+    if (offsets ? (n_spectra < 1 || n_spectra > 65535) : n_spectra != 1) return fail(HS_ERR_ARG, "n_spectra out of range");
+    if (radius < 0) return fail(HS_ERR_ARG, "radius < 0");
+    if (!(threshold == threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
+    if (((uintptr_t)snr & 3u)) return fail(HS_ERR_ARG, "misaligned snr");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hs::launch_zero_u64(cand_count, st);
+    if (e != hipSuccess) return fail_hip(e, "counter reset");
+    hs::PeakArgs a{};
+    a.snr = snr;
+    a.harm = harm;
+    a.drift = drift;
+    a.offsets = offsets;
+    a.n_bins = n_bins;
+    a.radius = radius;
+    a.thr = threshold;
+    a.cand = cand;
+    a.cap = cand_capacity;
+    a.count = cand_count;
+    e = hs::launch_peaks(a, offsets ? n_spectra : 1, offsets ? (n_bins + n_spectra - 1) / n_spectra : n_bins, st);
+    if (e != hipSuccess) return fail_hip(e, "peak kernel");
     return HS_OK;
 }
 

@@ -123,6 +123,20 @@ struct IlArgs {
     int32_t n_xcd;
 };
 
+// Peak clustering of dense outputs (see hs_pipeline.hip).
+struct PeakArgs {
+    const float *snr;
+    const uint8_t *harm;
+    const uint8_t *drift;     // NULL: drift 0 in the records
+    const int64_t *offsets;   // NULL: one spectrum of n_bins
+    int64_t n_bins;
+    int64_t radius;
+    float thr;
+    hs_candidate *cand;
+    int64_t cap;
+    unsigned long long *count;
+};
+
 // Persistent XCD-aware batched harmonic sum (see hs_sum_xcd.hip).
 struct XcdArgs {
     SumArgs s;                // offsets == NULL: one spectrum of s.n_bins
@@ -232,6 +246,8 @@ hipError_t launch_presto(const SumArgs &a, int hmax, int variant, bool f16, dim3
 hipError_t launch_stats_il(const StatsArgs &a, bool f16, hipStream_t st);
 hipError_t launch_sum_il(const IlArgs &a, int hmax, bool greedy, bool f16, hipStream_t st);
 hipError_t launch_interleave(const void *x, int64_t n_bins, int n_spectra, int elem_bytes, void *out, hipStream_t st);
+hipError_t launch_power(const void *fft, int64_t n, bool interbin, float sc, float sch, float *out, hipStream_t st);
+hipError_t launch_peaks(const PeakArgs &a, int groups, int64_t max_len, hipStream_t st);
 
 }  // namespace hs
 

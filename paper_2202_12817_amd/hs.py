@@ -28,7 +28,7 @@ EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_create_in", "hs_plan
             "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16",
             "hs_plan_set_timing", "hs_plan_get_timing", "hs_plan_set_graph", "hs_plan_graph_info",
             "hs_plan_set_launch", "hs_plan_get_launch", "hs_plan_tune_batched", "hs_status_string",
-            "hs_last_error", "hs_sum_interleaved", "hs_interleave"]
+            "hs_last_error", "hs_sum_interleaved", "hs_interleave", "hs_power_spectrum", "hs_cluster_peaks"]
 
 
 class HsPlanDesc(ctypes.Structure):
@@ -75,6 +75,8 @@ def load(path: str = LIB_PATH):
         lib.hs_get_norm.argtypes = [vp, i32, vp, vp, vp, vp]
         lib.hs_sum_interleaved.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         lib.hs_interleave.argtypes = [vp, i64, i32, i32, vp, vp]
+        lib.hs_power_spectrum.argtypes = [vp, i64, i32, ctypes.c_float, vp, vp]
+        lib.hs_cluster_peaks.argtypes = [vp, vp, vp, vp, i64, i32, i32, ctypes.c_float, vp, i64, vp, vp]
         lib.hs_quantize_f16.argtypes = [vp, i64, ctypes.c_float, vp, vp]
         lib.hs_plan_set_timing.argtypes = [vp, i32]
         lib.hs_plan_get_timing.argtypes = [vp, vp, vp, vp]
@@ -90,7 +92,8 @@ def load(path: str = LIB_PATH):
         for name in ("hs_plan_create", "hs_plan_create_in", "hs_plan_workspace_bytes", "hs_plan_destroy",
                      "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
                      "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
-                     "hs_plan_tune_batched", "hs_sum_interleaved", "hs_interleave"):
+                     "hs_plan_tune_batched", "hs_sum_interleaved", "hs_interleave", "hs_power_spectrum",
+                     "hs_cluster_peaks"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -185,6 +188,18 @@ def hs_sum_interleaved(plan, x, n_bins, n_spectra, norm, snr, harm, drift, cand=
 def hs_interleave(x, n_bins, n_spectra, elem_bytes, out, stream=None) -> None:
     _check(load().hs_interleave(_p(x), int(n_bins), int(n_spectra), int(elem_bytes), _p(out), _stream(stream)),
            "hs_interleave")
+
+
+def hs_power_spectrum(fft, n_bins, interbin, scale, out, stream=None) -> None:
+    _check(load().hs_power_spectrum(_p(fft), int(n_bins), int(interbin), float(scale), _p(out), _stream(stream)),
+           "hs_power_spectrum")
+
+
+def hs_cluster_peaks(snr, harm, drift, offsets, n_bins, n_spectra, radius, threshold, cand, cand_capacity,
+                     cand_count, stream=None) -> None:
+    _check(load().hs_cluster_peaks(_p(snr), _p(harm), _p(drift), _p(offsets), int(n_bins), int(n_spectra),
+                                   int(radius), float(threshold), _p(cand), int(cand_capacity), _p(cand_count),
+                                   _stream(stream)), "hs_cluster_peaks")
 
 
 def hs_get_norm(plan, n, mu_sigma, tables=None, valid=None, stream=None):

@@ -198,6 +198,28 @@ def sum_interleaved(x: torch.Tensor, H: int, mode="greedy", threshold=6.0, *, fi
     return out
 
 
+def power_spectrum(fft: torch.Tensor, interbin=False, scale=1.0, stream=None) -> torch.Tensor:
+    """Powers (float32) of complex64 FFT bins, inter-binned (2N - 1 values) or not."""
+    if fft.dtype != torch.complex64 or not fft.is_contiguous():
+        raise ValueError("fft must be contiguous complex64")
+    n = fft.numel()
+    out = torch.empty(2 * n - 1 if interbin else n, dtype=torch.float32, device=fft.device)
+    hs.hs_power_spectrum(fft, n, int(bool(interbin)), scale, out, stream)
+    return out
+
+
+def cluster_peaks(snr: torch.Tensor, harm: torch.Tensor, drift, threshold: float, radius: int, offsets=None,
+                  capacity=None, stream=None):
+    """Peak clustering of dense outputs (one spectrum, or a batch through device offsets)."""
+    n = snr.numel()
+    B = 1 if offsets is None else offsets.numel() - 1
+    cap = int(capacity) if capacity is not None else max(1024, n // 64)
+    cand = torch.empty((max(cap, 1), hs.CANDIDATE_BYTES // 4), dtype=torch.int32, device=snr.device)
+    count = torch.zeros(1, dtype=torch.int64, device=snr.device)
+    hs.hs_cluster_peaks(snr, harm, drift, offsets, n, B, radius, threshold, cand, cap, count, stream)
+    return dict(cand_raw=cand, count=count)
+
+
 def quantize_f16(x: torch.Tensor, scale: float, stream=None) -> torch.Tensor:
     """FP16 storage of float32 powers (binary16 patterns viewed as float16)."""
     out = torch.empty(x.numel(), dtype=torch.int16, device=x.device)

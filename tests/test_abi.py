@@ -93,6 +93,23 @@ def test_interleave_argument_checks_on_host(lib):
     assert lib.hs_interleave(p, 0, 4, 4, p, None) == hs.HS_ERR_ARG
 
 
+def test_pipeline_argument_checks_on_host(lib):
+    # argument checks of the pipeline calls run before anything is enqueued
+    from paper_2202_12817_amd import hs
+    buf = ctypes.create_string_buffer(256)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    q = ctypes.c_void_p(p.value + 1)
+    assert lib.hs_power_spectrum(None, 4, 0, 1.0, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_power_spectrum(p, 4, 1, 1.0, p, None) == hs.HS_ERR_ARG        # overlap
+    assert lib.hs_power_spectrum(q, 4, 0, 1.0, p, None) == hs.HS_ERR_ARG        # misaligned
+    assert lib.hs_power_spectrum(p, 0, 0, 1.0, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_power_spectrum(p, 4, 0, -1.0, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_cluster_peaks(None, p, None, None, 4, 1, 1, 1.0, p, 1, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_cluster_peaks(p, p, None, None, 4, 1, -1, 1.0, p, 1, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_cluster_peaks(p, p, None, None, 4, 2, 1, 1.0, p, 1, p, None) == hs.HS_ERR_ARG
+    assert lib.hs_cluster_peaks(p, p, None, p, 4, 0, 1, 1.0, p, 1, p, None) == hs.HS_ERR_ARG
+
+
 def test_masks_must_fit_h(lib):
     from paper_2202_12817_amd import hs
     h = ctypes.c_void_p()
