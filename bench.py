@@ -273,8 +273,49 @@ def table2_leg(hs, torch, dev, steps, warmup):
             res["H%d" % h] = r
         out[mname] = res
     out["interleaved"] = interleaved_leg(hs, torch, xt, ot, B, n_bins // B, snr, harm, steps, warmup, stream)
+    out["pipeline"] = pipeline_leg(hs, torch, xt, ot, B, n_bins, snr, harm, steps, stream)
     del xt, snr, harm
     return out
+
+
+def _event_ms(torch, stream, call, steps):
+    call()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        call()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def pipeline_leg(hs, torch, xt, ot, B, n_bins, snr, harm, steps, stream):
+    """The sum's neighbours at the same size: the inter-binned power spectrum of
+    n_bins complex FFT bins (8 B read, 8 B written per bin) and peak clustering
+    of the greedy H = 32 dense outputs (5 B read per bin + the window reads of
+    the candidates), HIP events on the launch stream."""
+    fft = torch.empty(n_bins, dtype=torch.complex64, device=xt.device)
+    fft.real.copy_(xt)
+    fft.imag.copy_(xt.flip(0))
+    pw = torch.empty(2 * n_bins - 1, dtype=torch.float32, device=xt.device)
+    ms_p = _event_ms(torch, stream, lambda: hs.hs_power_spectrum(fft, n_bins, 1, 1.0, pw, stream), steps)
+    del fft, pw
+    plan = hs.Plan(harmonics=32, mode=hs.HS_GREEDY, dtype=hs.HS_F32, max_spectra=B)
+    hs.hs_sum_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, stream)
+    torch.cuda.synchronize()
+    plan.close()
+    cap = 1 << 22
+    cand = torch.empty((cap, 4), dtype=torch.int32, device=xt.device)
+    count = torch.zeros(1, dtype=torch.int64, device=xt.device)
+    ms_c = _event_ms(torch, stream, lambda: hs.hs_cluster_peaks(snr, harm, None, ot, n_bins, B, 16, 6.0, cand, cap,
+                                                               count, stream), steps)
+    peaks = int(count.item())
+    bp, bc = 16.0 * n_bins, 5.0 * n_bins
+    return {"power_spectrum_interbinned": {"ms": ms_p, "gbs": bp / (ms_p * 1e-3) / 1e9,
+                                           "frac": bp / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "cluster_peaks_r16_snr6": {"ms": ms_c, "gbs": bc / (ms_c * 1e-3) / 1e9,
+                                       "frac": bc / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS, "peaks": peaks}}
 
 
 def _timed_sum(hs, torch, plan, call, steps, warmup):

@@ -197,6 +197,31 @@ __device__ __forceinline__ void stage_flush(Stage &st, hs_candidate *cand, int64
     st.count = 0;
 }
 
+// The end of a kernel: the records still staged by the workgroup's waves are
+// written with one atomic per workgroup instead of one per wave (the atomics
+// of all waves serialise on the counter's address).  Every thread of the
+// workgroup must call it (it synchronises the workgroup).
+template <int WAVES>
+__device__ __forceinline__ void stage_flush_block(Stage &st, hs_candidate *cand, int64_t cap,
+                                                  unsigned long long *count) {
+    __shared__ int s_cnt[WAVES];
+    __shared__ unsigned long long s_base;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s_cnt[w] = st.count;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int i = 0; i < WAVES; ++i) tot += s_cnt[i];
+        s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long base = s_base;
+    for (int i = 0; i < w; ++i) base += (unsigned long long)s_cnt[i];
+    for (int i = lane; i < st.count; i += 64)
+        if ((int64_t)(base + i) < cap) cand[base + i] = st.buf[i];
+    st.count = 0;
+}
+
 template <int SLICE>
 __device__ __forceinline__ void stage_push(Stage &st, hs_candidate *cand, int64_t cap, unsigned long long *count,
                                            bool pred, const hs_candidate &r) {

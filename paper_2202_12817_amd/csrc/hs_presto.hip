@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
             stage_push<kPrestoStage>(st, a.cand, a.cap, a.count, in && s.kb > 0 && snr > a.thr, rec);
         }
     }
-    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
+    if (a.cand) stage_flush_block<kBlock / 64>(st, a.cand, a.cap, a.count);
 }
 
 template <int HMAX, int VARIANT>

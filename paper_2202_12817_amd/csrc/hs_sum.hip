@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
             stage_push<kPlainStage>(st, a.cand, a.cap, a.count, in && b.harm > 0 && b.snr > a.thr, rec);
         }
     }
-    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
+    if (a.cand) stage_flush_block<kBlock / 64>(st, a.cand, a.cap, a.count);
 }
 
 // One column tile of row i: lane owns fundamental r.
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
     if (kz > a.H) kz = a.H;
     for (int64_t t = blockIdx.x; t * kBlock < a.n_r; t += gridDim.x)
         walk_2d_tile<HMAX, GREEDY, F16>(a, i, z, kz, t * kBlock + threadIdx.x, valid, tab, st);
-    if (a.cand) stage_flush(st, a.cand, a.cap, a.count);
+    if (a.cand) stage_flush_block<kBlock / 64>(st, a.cand, a.cap, a.count);
 }
 
 template <int HMAX>

@@ -46,7 +46,7 @@ def test_power_spectrum_bitwise(dev, n, interbin, scale):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
-@pytest.mark.parametrize("radius", [0, 1, 5, 64])
+@pytest.mark.parametrize("radius", [0, 1, 5, 64, 1024, 1025, 3000])
 @pytest.mark.parametrize("thr", [2.0, 4.0])
 def test_cluster_peaks_batched(dev, radius, thr):
     x, off = synthetic.config3(n_spectra=23, lo=2, hi=60000, seed=95)
