@@ -116,6 +116,58 @@ __device__ __forceinline__ void stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int
     if constexpr (K < HMAX) stages<VARIANT, F16, K + 1, HMAX>(r, n, H, first_bin, tab, kmask, s);
 }
 
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// PRESTO and PRESTO_all: every stage order K is a power of two, so the bin
+// nearest to h n / K is the bin nearest to (h HMAX / K) n / HMAX: all stages
+// read bins of the HMAX stage (HMAX, the compiled bucket, is a power of two
+// >= H).  Its HMAX bins are computed and loaded once (division by 2 HMAX is a
+// shift) and every stage sums its elements from registers, in increasing h.
+template <int VARIANT, bool F16, int HMAX>
+__device__ __forceinline__ void pow2_stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
+                                            const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
+    static_assert((HMAX & (HMAX - 1)) == 0, "bucket must be a power of two");
+    constexpr uint32_t eb = F16 ? 2u : 4u;
+    constexpr uint32_t sh = F16 ? 1u : 2u;
+    constexpr int lg = ilog2(2 * HMAX);
+    const uint32_t Q = n >> ilog2(HMAX);
+    const uint32_t R2 = 2u * (n & (uint32_t)(HMAX - 1));
+    const uint32_t Qb = Q * eb;
+    uint32_t off[HMAX + 1];                      // off[j]: byte offset of bin j of the HMAX stage
+    float v[HMAX + 1];
+    uint32_t hqb = 0, hr = (uint32_t)HMAX;       // j Q (bytes), 2 j R + HMAX
+#pragma unroll
+    for (int j = 1; j <= HMAX; ++j) {
+        hqb += Qb;
+        hr += R2;
+        asm("" : "+v"(hqb), "+v"(hr));
+        off[j] = hqb + ((hr >> lg) << sh);
+        v[j] = load_at<F16>(r, off[j]);
+    }
+    const uint32_t fb = first_bin * eb;
+#pragma unroll
+    for (int K = 2; K <= HMAX; K *= 2) {
+        if (K > H) break;
+        const int st = HMAX / K;                 // bin h of stage K is bin h st of the HMAX stage
+        if (off[st] < fb) break;                 // the stage's fundamental lies below first_bin
+        float S = v[st];
+#pragma unroll
+        for (int h = 2; h <= K; ++h) {
+            if (!harmonic_summed<VARIANT>(h)) continue;
+            S = S + v[h * st];
+        }
+        const int m = VARIANT == HS_PRESTO ? 1 + K / 2 : K;
+        const float2 t = tab[m - 1];
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        if ((kmask >> (K - 1)) & 1ull) {
+            if (s.kb == 0 || snr > s.best) {
+                s.best = snr;
+                s.kb = K;
+            }
+        }
+    }
+}
+
 constexpr int kPrestoStage = 64;   // candidate records staged per wave
 
 // 1D spectra: workgroup -> (tile block bx, spectrum sp) by batched_block
@@ -143,8 +195,12 @@ __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
         const int64_t n = t * kBlock + threadIdx.x;
         const bool in = n < len;
         StageState s{0.0f, 0, true};
-        if (in && valid && n >= a.first_bin && n < n_end)
-            stages<VARIANT, F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
+        if (in && valid && n >= a.first_bin && n < n_end) {
+            if constexpr (VARIANT == HS_PRESTO_PLUS)
+                stages<VARIANT, F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
+            else
+                pow2_stages<VARIANT, F16, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
+        }
         const float snr = s.kb ? s.best : 0.0f;
         if (in) {
             if (a.snr) a.snr[off + n] = snr;
