@@ -118,6 +118,63 @@ __device__ __forceinline__ void stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
+// Largest o 2^e <= HMAX (the top stage of the chain of odd part o).
+constexpr int chain_top(int o, int hmax) { return o * 2 > hmax ? o : chain_top(o * 2, hmax); }
+
+// PRESTO+: the stages o, 2 o, 4 o, ... (one chain per odd o) read bins of
+// their top stage T (bin h of stage K is bin h T / K of stage T), so each
+// chain computes and loads T bins once and sums its stages from registers in
+// h order.  Chains run in any order, so the best stage is chosen by the
+// larger SNR, ties to the smaller K (the in-order rule).
+template <bool F16, int O, int HMAX>
+__device__ __forceinline__ void plus_chain(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
+                                           const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
+    constexpr int T = chain_top(O, HMAX);
+    constexpr uint32_t eb = F16 ? 2u : 4u;
+    constexpr uint32_t sh = F16 ? 1u : 2u;
+    static_assert(2 * T * T - T < (1 << 11), "2 h R + T must stay below 2^11");
+    if (O > H) return;
+    const uint32_t fb = first_bin * eb;
+    const uint32_t Q = n / (uint32_t)T;
+    const uint32_t R2 = (2u * (n - Q * (uint32_t)T)) << 12;
+    const uint32_t Qb = Q * eb;
+    uint32_t off[T + 1];
+    float v[T + 1];
+    uint32_t hqb = 0, hr = (uint32_t)T << 12;
+#pragma unroll
+    for (int j = 1; j <= T; ++j) {
+        hqb += Qb;
+        hr += R2;
+        asm("" : "+v"(hqb), "+v"(hr));
+        off[j] = hqb + (div_2k<T>(hr) << sh);
+        v[j] = load_at<F16>(r, off[j]);
+    }
+#pragma unroll
+    for (int K = O; K <= T; K *= 2) {
+        if (K > H) break;
+        const int st = T / K;
+        if (off[st] < fb) break;                 // fundamentals only fall as K grows
+        float S = v[st];
+#pragma unroll
+        for (int h = 2; h <= K; ++h) S = S + v[h * st];
+        const float2 t = tab[K - 1];
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        if ((kmask >> (K - 1)) & 1ull) {
+            if (s.kb == 0 || snr > s.best || (snr == s.best && K < s.kb)) {
+                s.best = snr;
+                s.kb = K;
+            }
+        }
+    }
+}
+
+template <bool F16, int O, int HMAX>
+__device__ __forceinline__ void plus_chains(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
+                                            const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
+    plus_chain<F16, O, HMAX>(r, n, H, first_bin, tab, kmask, s);
+    if constexpr (O + 2 <= HMAX) plus_chains<F16, O + 2, HMAX>(r, n, H, first_bin, tab, kmask, s);
+}
+
 // PRESTO and PRESTO_all: every stage order K is a power of two, so the bin
 // nearest to h n / K is the bin nearest to (h HMAX / K) n / HMAX: all stages
 // read bins of the HMAX stage (HMAX, the compiled bucket, is a power of two
@@ -197,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
         StageState s{0.0f, 0, true};
         if (in && valid && n >= a.first_bin && n < n_end) {
             if constexpr (VARIANT == HS_PRESTO_PLUS)
-                stages<VARIANT, F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
+                plus_chains<F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
             else
                 pow2_stages<VARIANT, F16, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
         }
