@@ -141,14 +141,24 @@ __device__ __forceinline__ void plus_chain(__amdgpu_buffer_rsrc_t r, uint32_t n,
     uint32_t off[T + 1];
     float v[T + 1];
     uint32_t hqb = 0, hr = (uint32_t)T << 12;
+    // odd T: 2 j R + T is odd, never a multiple of 2 T, so no bin is an exact
+    // half and bin T - j is n - bin j (one subtraction instead of four steps)
+    constexpr int direct = (T % 2 == 1) ? (T - 1) / 2 : T;
 #pragma unroll
-    for (int j = 1; j <= T; ++j) {
+    for (int j = 1; j <= direct; ++j) {
         hqb += Qb;
         hr += R2;
         asm("" : "+v"(hqb), "+v"(hr));
         off[j] = hqb + (div_2k<T>(hr) << sh);
-        v[j] = load_at<F16>(r, off[j]);
     }
+    if constexpr (T % 2 == 1) {
+        const uint32_t nb = n * eb;
+#pragma unroll
+        for (int j = 1; j <= direct; ++j) off[T - j] = nb - off[j];
+        off[T] = nb;
+    }
+#pragma unroll
+    for (int j = 1; j <= T; ++j) v[j] = load_at<F16>(r, off[j]);
 #pragma unroll
     for (int K = O; K <= T; K *= 2) {
         if (K > H) break;
