@@ -11,34 +11,28 @@
 // the walk); the best stage is the largest SNR among the stages the mask
 // selects, ties to the smaller K.
 //
-// One lane owns one last bin n.  With n = Q K + R (0 <= R < K) the bin of
-// harmonic h is  h Q + floor((2 h R + K) / (2 K)):  h Q and 2 h R + K are
-// carried from one harmonic to the next by additions, and the small quotient
-// (numerator 2 h R + K <= 2 K^2 - K < 2^11) is floor(x ceil(2^20 / 2K) / 2^20),
-// exact for every numerator below 2^11 and every K <= 32 (checked
-// exhaustively), taken as the high word of a 24-bit multiply.  K is a
-// compile-time constant in every stage, so n / K is a multiply-high or a
-// shift.  Consecutive lanes own consecutive
-// bins; harmonic h of a wave reads about 64 h / K consecutive bins, so every
-// gather is nearly contiguous.
+// One lane owns one last bin n; consecutive lanes own consecutive bins, so a
+// stage's harmonic h reads about 64 h / K consecutive bins per wave.  Stages
+// share bins: the bin nearest to h n / K is bin h T / K of any stage T that
+// is a multiple of K by a power of two.  So PRESTO and PRESTO_all (orders 2,
+// 4, ...) read the bins of the compiled power-of-two bucket's stage once, and
+// PRESTO+ groups its orders into chains o, 2 o, 4 o, ... (o odd) that read
+// the bins of their top order once; every stage then sums from registers in
+// increasing h (the same float sums as stage-by-stage).  With n = Q T + R
+// (0 <= R < T) bin j of stage T is  j Q + floor((2 j R + T) / (2 T)):  j Q
+// and 2 j R + T are carried from bin to bin by additions, and the small
+// quotient (numerator <= 2 T^2 - T < 2^11) is floor(x ceil(2^20 / 2T) / 2^20),
+// exact for every numerator below 2^11 and every T <= 32 (checked
+// exhaustively), the high word of a 24-bit multiply (a shift when T is a
+// power of two).
 #include "hs_internal.h"
 
 namespace hs {
 namespace {
 
-template <int VARIANT, int K>
-constexpr bool stage_formed() {
-    return VARIANT == HS_PRESTO_PLUS || (K >= 2 && (K & (K - 1)) == 0);
-}
-
 template <int VARIANT>
 constexpr bool harmonic_summed(int h) {
     return VARIANT != HS_PRESTO || h == 1 || h % 2 == 0;
-}
-
-template <int VARIANT, int K>
-constexpr int stage_elems() {
-    return VARIANT == HS_PRESTO ? 1 + K / 2 : K;
 }
 
 // floor(x / (2 K)) for x < 2^11, given x12 = x 2^12 (< 2^23): the high word
@@ -63,58 +57,9 @@ __device__ __forceinline__ float load_at(__amdgpu_buffer_rsrc_t r, uint32_t byte
 }
 
 struct StageState {
-    float best;
-    int kb;
-    bool live;    // every earlier stage's fundamental was >= first_bin
+    float best;   // best SNR so far (valid when kb > 0)
+    int kb;       // its stage order, 0 = none
 };
-
-// Stage K of last bin n.
-template <int VARIANT, bool F16, int K>
-__device__ __forceinline__ void stage(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
-                                      const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
-    if constexpr (stage_formed<VARIANT, K>()) {
-        if (!s.live || K > H) return;
-        constexpr uint32_t eb = F16 ? 2u : 4u;
-        constexpr uint32_t sh = F16 ? 1u : 2u;
-        static_assert(2 * K * K - K < (1 << 11), "2 h R + K must stay below 2^11");
-        const uint32_t Q = n / (uint32_t)K;
-        const uint32_t R2 = (2u * (n - Q * (uint32_t)K)) << 12;   // step of (2 h R + K) 2^12
-        const uint32_t Qb = Q * eb;                               // step of h Q, in bytes
-        uint32_t hqb = Qb;                                        // h = 1
-        uint32_t hr = R2 + ((uint32_t)K << 12);
-        const uint32_t fd = div_2k<K>(hr);
-        if (Q + fd < first_bin) {     // the fundamental
-            s.live = false;
-            return;
-        }
-        float S = load_at<F16>(r, hqb + (fd << sh));
-#pragma unroll
-        for (int h = 2; h <= K; ++h) {
-            // carried by additions (kept opaque so that they stay one add each)
-            hqb += Qb;
-            hr += R2;
-            asm("" : "+v"(hqb), "+v"(hr));
-            if (!harmonic_summed<VARIANT>(h)) continue;
-            S = S + load_at<F16>(r, hqb + (div_2k<K>(hr) << sh));
-        }
-        constexpr int m = stage_elems<VARIANT, K>();
-        const float2 t = tab[m - 1];
-        const float snr = __builtin_fmaf(S, t.x, t.y);
-        if ((kmask >> (K - 1)) & 1ull) {
-            if (s.kb == 0 || snr > s.best) {
-                s.best = snr;
-                s.kb = K;
-            }
-        }
-    }
-}
-
-template <int VARIANT, bool F16, int K, int HMAX>
-__device__ __forceinline__ void stages(__amdgpu_buffer_rsrc_t r, uint32_t n, int H, uint32_t first_bin,
-                                       const float2 *__restrict__ tab, uint64_t kmask, StageState &s) {
-    stage<VARIANT, F16, K>(r, n, H, first_bin, tab, kmask, s);
-    if constexpr (K < HMAX) stages<VARIANT, F16, K + 1, HMAX>(r, n, H, first_bin, tab, kmask, s);
-}
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
@@ -261,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_presto(SumArgs a) {
     for (int64_t t = bx; t * kBlock < len; t += gridDim.x) {
         const int64_t n = t * kBlock + threadIdx.x;
         const bool in = n < len;
-        StageState s{0.0f, 0, true};
+        StageState s{0.0f, 0};
         if (in && valid && n >= a.first_bin && n < n_end) {
             if constexpr (VARIANT == HS_PRESTO_PLUS)
                 plus_chains<F16, 1, HMAX>(rsrc, (uint32_t)n, a.H, (uint32_t)a.first_bin, tab, a.kmask, s);
