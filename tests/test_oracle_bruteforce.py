@@ -46,6 +46,18 @@ def _best(sums, mu, sig2):
     return best
 
 
+def _check_choice(r, n, sums, mu, sigma, kb, tol):
+    """The chosen harmonic count is the exact argmax kb, or one whose exact SNR
+    ties kb's within the precision's rounding (the float tables of different
+    counts are rounded separately, so an exact tie can break either way)."""
+    got = int(r["harm"][n])
+    snr = lambda k: (float(sums[k - 1]) - k * mu) / (math.sqrt(k) * sigma)   # noqa: E731
+    assert 1 <= got <= len(sums), (n, got)
+    if got != kb:
+        assert abs(snr(got) - snr(kb)) <= tol * max(1, abs(snr(kb))), (n, kb, got)
+    return got
+
+
 def _keff(n, N, H, greedy):
     if n < 1:
         return 0
@@ -99,7 +111,11 @@ def test_standard_bruteforce(vals, H, seed):
         for k in range(H):
             assert r64["partial"][k, n] == (float(sums[k]) if k < K else 0.0)
         kb = _best(sums, mu, sigma * sigma) if K else 0
-        assert r64["harm"][n] == kb and r32["harm"][n] == kb
+        if kb:
+            _check_choice(r64, n, sums, mu, sigma, kb, 1e-12)
+            _check_choice(r32, n, sums, mu, sigma, kb, 2e-6)
+        else:
+            assert r64["harm"][n] == 0 and r32["harm"][n] == 0
         assert r64["drift"][n] == 0 and r32["drift"][n] == 0
         if kb:
             want = (float(sums[kb - 1]) - kb * mu) / (math.sqrt(kb) * sigma)
@@ -126,8 +142,9 @@ def test_greedy_bruteforce_tree(vals, H):
         for k in range(K):
             assert r64["partial"][k, n] == float(sums[k])
         kb = _best(sums, mu, sigma * sigma)
-        assert r64["harm"][n] == kb and r32["harm"][n] == kb
-        assert r64["drift"][n] == sum(bits[:kb]) == r32["drift"][n]
+        g64 = _check_choice(r64, n, sums, mu, sigma, kb, 1e-12)
+        g32 = _check_choice(r32, n, sums, mu, sigma, kb, 2e-6)
+        assert r64["drift"][n] == sum(bits[:g64]) and r32["drift"][n] == sum(bits[:g32])
         # both bins read at every step stay inside the spectrum
         assert all(k * n + sum(bits[:k - 1]) + 1 <= N - 1 for k in range(1, K + 1))
 
