@@ -14,9 +14,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hs_oracle.c")
-PINS = ["tests/test_oracle_golden.py", "tests/test_oracle_stats.py", "tests/test_oracle_bruteforce.py",
-        "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py", "tests/test_oracle_presto.py",
-        "tests/test_oracle_pipeline.py"]
+PINS = ["tests/test_oracle_pipeline.py", "tests/test_oracle_golden.py", "tests/test_oracle_stats.py",
+        "tests/test_oracle_bruteforce.py", "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py",
+        "tests/test_oracle_presto.py"]
 
 C_MUTANTS = {
     "greedy-tie-moves": ("if (b > a) { d += 1; v = b; }", "if (b >= a) { d += 1; v = b; }"),
