@@ -174,3 +174,29 @@ def test_table2_workload_interleaved_sampled(dev, mode):
         wc = oracle.candidates(w32["snr"], w32["harm"], w32["drift"], 6.0, spectrum=s)
         assert _same_records(recs[recs["spectrum"] == s], wc), s
     del xi, got
+
+
+@pytest.mark.slow
+def test_interleaved_max_size(dev):
+    """The largest interleaved array a call accepts: 1024 spectra of 2^20 - 1
+    bins (n_bins * n_spectra just below 2^30, 4 GiB FP32), greedy H = 32:
+    every row offset stays in 32 bits; sampled spectra (first, last, middle)
+    against the oracle, exact statistics."""
+    B, N = 1024, (1 << 20) - 1
+    x = synthetic.exp_noise(B * N, 98).reshape(N, B)          # already interleaved: bin-major
+    xt = torch.from_numpy(x).to(dev)
+    print("interleaved max size", flush=True)
+    got = _ops().sum_interleaved(xt, 32, "greedy", 6.0, dense=True, candidates=True, capacity=1 << 24,
+                                 with_norm=True)
+    ms = _np(got["mu_sigma"])
+    recs, n = _cands(got)
+    assert n == recs.size
+    for s in (0, 511, 1023):
+        col = np.ascontiguousarray(x[:, s])
+        w = oracle.hs_1d(col, 32, oracle.GREEDY)
+        assert (ms[s, 0], ms[s, 1]) == (w["mu1"], w["sigma1"])
+        check_dense({k: got[k][:, s].contiguous().cpu() for k in ("snr", "harm", "drift")}, w, None,
+                    "max size spectrum %d" % s)
+        wc = oracle.candidates(w["snr"], w["harm"], w["drift"], 6.0, spectrum=s)
+        assert _same_records(recs[recs["spectrum"] == s], wc), s
+    del xt, got

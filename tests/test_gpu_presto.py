@@ -156,3 +156,25 @@ def test_table2_workload_sampled(dev, mode):
         wc = oracle.candidates(w32["snr"], w32["harm"], w32["drift"], 6.0, spectrum=s)
         assert _same_records(recs[recs["spectrum"] == s], wc), s
     del xt, got
+
+
+@pytest.mark.slow
+def test_presto_plus_max_length(dev):
+    """PRESTO+ (and PRESTO) on the longest spectrum a call accepts, 2^30 - 1
+    FP32 bins, H = 32: every bin offset of every chain stays in 32 bits;
+    sampled last bins (both ends, random) against the oracle."""
+    n = (1 << 30) - 1
+    x = synthetic.exp_noise(n, 94)
+    mu1, sigma1 = oracle.norm_from_data(x, 1)
+    xt = torch.from_numpy(x).to(dev)
+    g = np.random.default_rng(94)
+    idx = np.unique(np.concatenate([np.arange(0, 2000), np.arange(n - 2000, n), g.integers(0, n, 20000)]))
+    it = torch.from_numpy(idx).to(dev)
+    for mode in ("presto_plus", "presto"):
+        print("presto max length", mode, flush=True)
+        w = oracle.hs_1d(x, 32, MODES[mode], norm=(mu1, sigma1), idx=idx)
+        got = _ops().sum_1d(xt, 32, mode, with_norm=True)
+        ms = _np(got["mu_sigma"])[0]
+        assert (ms[0], ms[1]) == (mu1, sigma1)
+        check_dense({k: got[k][it] for k in ("snr", "harm", "drift")}, w, None, "max length " + mode)
+        del got
