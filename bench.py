@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--spectra", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and FP16 legs")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="spectra in the CPU oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=72, help="spectra in the CPU oracle sample (about 10-15 s of one core)")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file of the tuner (default: tune afresh)")
     ap.add_argument("--launch", default=None, metavar="F,W",
                     help="fixed launch shape (fundamentals per lane, workgroups per CU) instead of tuning")
