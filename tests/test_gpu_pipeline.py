@@ -46,6 +46,17 @@ def test_power_spectrum_bitwise(dev, n, interbin, scale):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
+def test_power_spectrum_unaligned_output(dev):
+    # an output 4 but not 8 bytes aligned takes the single-float stores
+    F = (np.random.default_rng(99).normal(size=4097) + 1j).astype(np.complex64)
+    buf = torch.zeros(2 * F.size + 2, dtype=torch.float32, device=dev)
+    from paper_2202_12817_amd import hs
+    hs.hs_power_spectrum(torch.from_numpy(F).to(dev), F.size, 1, 0.5, buf.data_ptr() + 4)
+    got = _np(buf)[1:1 + 2 * F.size - 1]
+    assert np.array_equal(got.view(np.uint32), oracle.power_spectrum(F, True, 0.5).view(np.uint32))
+    assert _np(buf)[0] == 0 and _np(buf)[-1] == 0
+
+
 @pytest.mark.parametrize("radius", [0, 1, 5, 64, 1024, 1025, 3000])
 @pytest.mark.parametrize("thr", [2.0, 4.0])
 def test_cluster_peaks_batched(dev, radius, thr):
