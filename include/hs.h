@@ -27,8 +27,8 @@
  *   the bin nearest to n / harm), drift = 0, harmonic_mask bit K-1 selects
  *   stage K, fundamental_end bounds the last bin.  These modes run one kernel
  *   (kernel AUTO or PLAIN), support hs_sum_1d without report_mask and
- *   hs_sum_batched, and return HS_ERR_UNSUPPORTED from hs_sum_2d, the launch
- *   shape calls and the tuner.
+ *   hs_sum_batched with H <= 32, and return HS_ERR_UNSUPPORTED from
+ *   hs_sum_2d, the launch shape calls and the tuner.
  *
  * Conventions shared by every entry point:
  *
@@ -39,8 +39,14 @@
  *     sigma_k = sqrt(k) sigma1.  The float SNR of a k-element sum is
  *     fmaf(S_k, rs_k, nm_k) with rs_k = (float)(1/sigma_k) and
  *     nm_k = (float)(-(mu_k/sigma_k)); S_k is summed in float in harmonic
- *     order.  A caller may supply (mu1, sigma1) instead (`norm` arguments).
- *     sigma1 zero or not finite: every output of that spectrum is zero.
+ *     order.  A caller may supply (mu1, sigma1) instead (`norm` arguments),
+ *     or, with hs_plan_desc.norm_kind = HS_NORM_TABLE, the whole per-k table
+ *     (mu_k, sigma_k for k = 1..H; Eq. (2) normalises the k-element sum by
+ *     the mean and deviation of a k-element sum, which a caller may have
+ *     calibrated on its own null): then rs_k = (float)(1/sigma_k) and
+ *     nm_k = (float)(-(mu_k/sigma_k)).  sigma1 (any sigma_k of a table) zero
+ *     or not finite, or a mean not finite: every output of that spectrum is
+ *     zero.
  *   - Truncation: harmonic k of fundamental n is summed only while every bin it
  *     may read is inside the spectrum: k n <= N-1 (simple), k (n+1) <= N-1
  *     (greedy).  Bins below first_bin or at/after fundamental_end are no
@@ -77,9 +83,10 @@ extern "C" {
 typedef enum hs_status {
     HS_OK = 0,
     HS_ERR_ARG = 1,          /* invalid argument (null pointer, size or range) */
-    HS_ERR_UNSUPPORTED = 2,  /* valid but not supported by this build (e.g. H > 32) */
+    HS_ERR_UNSUPPORTED = 2,  /* valid but not supported by this build (e.g. H > 64) */
     HS_ERR_HIP = 3,          /* a HIP runtime call failed */
-    HS_ERR_NOMEM = 4         /* device allocation of the plan workspace failed */
+    HS_ERR_NOMEM = 4,        /* an allocation failed (the plan's device workspace, or host memory) */
+    HS_ERR_INTERNAL = 5      /* unexpected failure inside the library (no exception crosses the ABI) */
 } hs_status;
 
 enum { HS_STANDARD = 0, HS_GREEDY = 1,          /* hs_plan_desc.mode */
@@ -96,12 +103,18 @@ enum { HS_F32 = 0, HS_F16 = 1 };           /* hs_plan_desc.dtype: stored power t
  * there).  hs_sum_1d with report_mask always runs PLAIN.  All give the same
  * results, bit for bit. */
 enum { HS_KERNEL_AUTO = 0, HS_KERNEL_PERSISTENT = 1, HS_KERNEL_PLAIN = 2 };
+/* hs_plan_desc.norm_kind: what the `norm` argument of the sum calls holds
+ * when it is not NULL.  MU_SIGMA: [2] doubles (mu1, sigma1) per spectrum
+ * (plane); the k-element sum uses mu_k = k mu1, sigma_k = sqrt(k) sigma1.
+ * TABLE: [2][H] doubles per spectrum (plane): mu_1..mu_H, then
+ * sigma_1..sigma_H, used as given; norm must then not be NULL. */
+enum { HS_NORM_MU_SIGMA = 0, HS_NORM_TABLE = 1 };
 
-#define HS_MAX_HARMONICS 32
+#define HS_MAX_HARMONICS 64
 
 /* Plan parameters.  Fill with hs_plan_desc_init, then override. */
 typedef struct hs_plan_desc {
-    int32_t  harmonics;        /* H, 1..HS_MAX_HARMONICS (default 32) */
+    int32_t  harmonics;        /* H, 1..HS_MAX_HARMONICS (default 32; PRESTO modes: 1..32) */
     int32_t  mode;             /* HS_STANDARD, HS_GREEDY (default) or a PRESTO mode */
     int32_t  dtype;            /* HS_F32 or HS_F16 (IEEE binary16 storage, decoded exactly) */
     int32_t  first_bin;        /* >= 1; lowest fundamental and lowest bin in the statistics (default 1) */
@@ -111,6 +124,7 @@ typedef struct hs_plan_desc {
     int32_t  max_spectra;      /* hs_sum_batched: most spectra per call (default 1024) */
     float    threshold;        /* candidates: snr > threshold (default 6) */
     int32_t  kernel;           /* HS_KERNEL_AUTO (default), HS_KERNEL_PERSISTENT or HS_KERNEL_PLAIN */
+    int32_t  norm_kind;        /* HS_NORM_MU_SIGMA (default) or HS_NORM_TABLE: layout of `norm` */
 } hs_plan_desc;
 
 /* One candidate: a bin whose best SNR is strictly above the threshold. */
@@ -159,7 +173,8 @@ hs_status hs_plan_destroy(hs_plan *plan);
 /*
  * One spectrum (Eq. (3) or Algorithm 2 over all of its bins).
  *   x        [n_bins] powers, dtype of the plan.  2 <= n_bins < 2^30.
- *   norm     NULL: statistics from x; else [2] doubles (mu1, sigma1).
+ *   norm     NULL: statistics from x; else [2] doubles (mu1, sigma1), or
+ *            [2][H] doubles (mu_k, then sigma_k) with HS_NORM_TABLE.
  *   snr      [n_bins] float, harm [n_bins] uint8, drift [n_bins] uint8: dense
  *            outputs indexed by fundamental bin; drift may be NULL.
  *   partial  NULL, or [popcount(report_mask)][n_bins] floats: S_k for each
@@ -176,7 +191,8 @@ hs_status hs_sum_1d(hs_plan *plan, const void *x, int64_t n_bins, const double *
  *              spectrum 2 <= length < 2^30.  (Lengths are read on the device
  *              and not re-validated there: keep them within these bounds.)
  *   n_spectra  1..max_spectra of the plan (max_spectra <= 65535).
- *   norm       NULL or [2 n_spectra] doubles (mu1, sigma1 per spectrum).
+ *   norm       NULL or [n_spectra][2] doubles (mu1, sigma1 per spectrum), or
+ *              [n_spectra][2][H] doubles with HS_NORM_TABLE.
  *   snr/harm/drift  NULL, or dense outputs indexed like x.
  *   cand       NULL, or [cand_capacity] records of every bin with snr >
  *              threshold, in unspecified order; *cand_count (device, zeroed
@@ -196,7 +212,7 @@ hs_status hs_sum_batched(hs_plan *plan, const void *x, const int64_t *offsets, i
  *   plane      row i (z = z_min + i) starts at plane + i * row_stride; n_r
  *              columns.  row_stride >= n_r.  2 <= n_r < 2^30.
  *   z_min <= 0 <= z_max is not required; rows are z_min..z_max.
- *   norm       NULL or [2] doubles.
+ *   norm       NULL or [2] doubles (mu1, sigma1), or [2][H] with HS_NORM_TABLE.
  *   snr/harm/drift  NULL, or dense [n_z][n_r] outputs (row stride n_r).
  *   cand/cand_capacity/cand_count  as for hs_sum_batched (bin = i * n_r + r).
  */
@@ -215,7 +231,8 @@ hs_status hs_sum_2d(hs_plan *plan, const void *plane, int64_t n_r, int64_t row_s
  * spectra stored one after another.  The plan's kernel choice is ignored.
  *   x          [n_bins][n_spectra] powers, dtype of the plan; n_bins >= 2,
  *              n_bins * n_spectra < 2^30, 1 <= n_spectra <= max_spectra.
- *   norm       NULL or [2 n_spectra] doubles (mu1, sigma1 per spectrum).
+ *   norm       NULL or [n_spectra][2] doubles (mu1, sigma1 per spectrum), or
+ *              [n_spectra][2][H] with HS_NORM_TABLE.
  *   snr/harm/drift  NULL, or dense [n_bins][n_spectra] outputs (interleaved
  *              like x); drift may be NULL.
  *   cand/cand_capacity/cand_count  as for hs_sum_batched (spectrum = s,
@@ -272,7 +289,8 @@ hs_status hs_cluster_peaks(const float *snr, const uint8_t *harm, const uint8_t 
 /*
  * Export the normalisation used by the most recent sum call on this plan
  * (stream-ordered device-to-device copy of its first n entries).
- *   mu_sigma  [2 n] doubles (mu1, sigma1); tables NULL or [n][2][H] floats
+ *   mu_sigma  [2 n] doubles (mu1, sigma1; with HS_NORM_TABLE mu_1 and
+ *             sigma_1 of the caller's table); tables NULL or [n][2][H] floats
  *             (rs_k for k = 1..H, then nm_k for k = 1..H); valid NULL or [n]
  *             int32 (1 = usable normalisation, 0 = degenerate: zero outputs).
  */
@@ -318,8 +336,9 @@ hs_status hs_plan_graph_info(hs_plan *plan, int64_t *captures, int64_t *replays)
 
 /*
  * Launch shape of the persistent kernel (hs_sum_batched and the persistent
- * hs_sum_1d): fundamentals per lane (2 or 4) and resident workgroups of 256
- * threads per CU (1..4, bounded by the kernel's occupancy); for a plan with
+ * hs_sum_1d): fundamentals per lane (1, 2 or 4) and resident workgroups of
+ * 256 threads per CU (1..4 for 2 and 4 fundamentals per lane, 1..8 for one,
+ * bounded by the kernel's occupancy); for a plan with
  * HS_KERNEL_AUTO, fundamentals_per_lane 0 makes hs_sum_batched run the plain
  * kernel (workgroups_per_cu ignored; hs_plan_get_launch reports 0, 0).  The
  * results do not depend on the shape.  Default: 4 and the occupancy limit

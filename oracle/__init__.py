@@ -45,9 +45,9 @@ from fractions import Fraction
 import numpy as np
 
 __all__ = [
-    "build", "exact_sums", "stats", "norm_from_data", "tables", "is_degenerate",
-    "keff", "hs_1d", "hs_2d", "hs_batched", "candidates", "quantize_f16",
-    "GREEDY", "STANDARD", "PRESTO", "PRESTO_ALL", "PRESTO_PLUS", "presto_stages",
+    "build", "exact_sums", "stats", "norm_from_data", "tables", "caller_tables", "is_degenerate",
+    "hs_1d", "hs_2d", "hs_batched", "candidates", "quantize_f16",
+    "GREEDY", "STANDARD", "PRESTO", "PRESTO_ALL", "PRESTO_PLUS",
     "power_spectrum", "cluster_peaks", "INTERBIN_FACTOR",
 ]
 
@@ -187,12 +187,28 @@ def tables(mu1: float, sigma1: float, H: int):
     return mu, sig, rs, nm
 
 
-def keff(n: int, length: int, H: int, mode: int) -> int:
-    """Harmonics summed for fundamental ``n``: reads stay below ``length``."""
-    if n < 1:
-        return 0
-    reach = n + 1 if mode == GREEDY else n
-    return min(H, (length - 1) // reach)
+def caller_tables(mu_k, sigma_k):
+    """Per-k normalisation supplied by the caller (Eq. (2): the k-element sum
+    is normalised by the mean and deviation of a k-element sum, here given
+    for each k instead of derived from the one-bin statistics).
+
+    Returns ``(mu, sig, rs, nm, usable)``: the float64 tables as given, the
+    float32 ``rs_k = 1/sigma_k`` and ``nm_k = -(mu_k/sigma_k)`` (each operation
+    rounded once in float64, then once to float32), and whether every entry
+    is finite with every ``sigma_k > 0`` (otherwise every output is zero).
+    """
+    mu = np.array(mu_k, dtype=np.float64).reshape(-1)
+    sig = np.array(sigma_k, dtype=np.float64).reshape(-1)
+    if mu.size != sig.size or mu.size < 1:
+        raise ValueError("mu_k and sigma_k need one entry per k")
+    usable = bool(np.all(np.isfinite(mu)) and np.all(np.isfinite(sig)) and np.all(sig > 0.0))
+    rs = np.zeros(mu.size, dtype=np.float32)
+    nm = np.zeros(mu.size, dtype=np.float32)
+    if usable:
+        for i in range(mu.size):
+            rs[i] = np.float32(1.0 / float(sig[i]))
+            nm[i] = np.float32(-(float(mu[i]) / float(sig[i])))
+    return mu, sig, rs, nm, usable
 
 
 # ---------------------------------------------------------------------------
@@ -203,27 +219,6 @@ def _kmask(mask: int, H: int) -> int:
     return ((1 << H) - 1) if not mask else (mask & ((1 << H) - 1))
 
 
-def presto_stages(n: int, H: int, mode: int, first_bin: int = 1):
-    """Stages ``(K, m)`` formed for last bin ``n`` (``m`` = elements summed).
-
-    Sec. 3.2: PRESTO takes the power-of-two orders from 2 and sums the
-    fundamental and the even harmonics (m = 1 + K/2); PRESTO_all the same
-    orders with every harmonic; PRESTO+ every order 1..H with every harmonic.
-    A stage is formed only if its fundamental, the bin nearest to n / K, is
-    not below ``first_bin``.
-    """
-    out = []
-    if n < first_bin:
-        return out
-    for K in range(1, H + 1):
-        if mode != PRESTO_PLUS and not (K >= 2 and K & (K - 1) == 0):
-            continue
-        if (2 * n + K) // (2 * K) < first_bin:
-            continue
-        out.append((K, 1 + K // 2 if mode == PRESTO else K))
-    return out
-
-
 def _check(H, mode, modes=(STANDARD, GREEDY, PRESTO, PRESTO_ALL, PRESTO_PLUS)):
     if not (1 <= H <= MAX_H):
         raise ValueError("H out of range")
@@ -232,10 +227,12 @@ def _check(H, mode, modes=(STANDARD, GREEDY, PRESTO, PRESTO_ALL, PRESTO_PLUS)):
 
 
 def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
-          precision="f32", norm=None, idx=None, report=()):
+          precision="f32", norm=None, norm_table=None, idx=None, report=()):
     """Harmonic sum of one spectrum.
 
-    ``norm``: ``(mu1, sigma1)`` to use instead of the statistics of ``x``.
+    ``norm``: ``(mu1, sigma1)`` to use instead of the statistics of ``x``;
+    ``norm_table``: ``(mu_k, sigma_k)``, two sequences of H values, used as
+    given for the k-element sums (see :func:`caller_tables`).
     ``idx``: fundamentals to evaluate (default: every bin, output index = bin).
     ``report``: harmonic counts K whose partial sums are returned (zero where a
     fundamental sums fewer than K harmonics; simple and greedy sums only).
@@ -250,7 +247,13 @@ def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
         raise ValueError("partial sums are reported for the simple and greedy sums only")
     x = np.ascontiguousarray(x, dtype=np.float32)
     N = x.size
-    if norm is None:
+    tab = None
+    if norm_table is not None:
+        tab = caller_tables(norm_table[0], norm_table[1])
+        if tab[0].size != H:
+            raise ValueError("norm_table needs H entries")
+        mu1, sigma1 = float(tab[0][0]), float(tab[1][0])
+    elif norm is None:
         mu1, sigma1 = norm_from_data(x, first_bin)
     else:
         mu1, sigma1 = float(norm[0]), float(norm[1])
@@ -263,9 +266,9 @@ def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
     rep = np.ascontiguousarray(list(report), dtype=np.int32)
     partial = np.zeros((len(rep), n_out), dtype=snr.dtype) if len(rep) else None
     out = dict(snr=snr, harm=harm, drift=drift, partial=partial, mu1=mu1, sigma1=sigma1)
-    if is_degenerate(mu1, sigma1) or n_out == 0:
+    if (not tab[4] if tab is not None else is_degenerate(mu1, sigma1)) or n_out == 0:
         return out
-    mu, sig, rs, nm = tables(mu1, sigma1, H)
+    mu, sig, rs, nm = tab[:4] if tab is not None else tables(mu1, sigma1, H)
     n_end = N if not fundamental_end else min(N, int(fundamental_end))
     lib = _load()
     t1, t2 = (mu, sig) if f64 else (rs, nm)
@@ -282,7 +285,7 @@ def hs_1d(x, H, mode, *, first_bin=1, fundamental_end=0, harmonic_mask=0,
 
 
 def hs_2d(plane, z_min, z_max, H, mode, *, first_bin=1, fundamental_end=0,
-          harmonic_mask=0, precision="f32", norm=None, idx=None):
+          harmonic_mask=0, precision="f32", norm=None, norm_table=None, idx=None):
     """Harmonic sum of an f-fdot plane (rows ``z_min..z_max``, row-major).
 
     Harmonic k of fundamental (r, z) reads row ``k z`` at column ``k r`` (plus
@@ -295,7 +298,13 @@ def hs_2d(plane, z_min, z_max, H, mode, *, first_bin=1, fundamental_end=0,
     n_z, n_r = p.shape
     if n_z != z_max - z_min + 1:
         raise ValueError("plane rows do not match z range")
-    if norm is None:
+    tab = None
+    if norm_table is not None:
+        tab = caller_tables(norm_table[0], norm_table[1])
+        if tab[0].size != H:
+            raise ValueError("norm_table needs H entries")
+        mu1, sigma1 = float(tab[0][0]), float(tab[1][0])
+    elif norm is None:
         mu1, sigma1 = norm_from_data(p, first_bin)
     else:
         mu1, sigma1 = float(norm[0]), float(norm[1])
@@ -306,9 +315,9 @@ def hs_2d(plane, z_min, z_max, H, mode, *, first_bin=1, fundamental_end=0,
     harm = np.zeros(n_out, dtype=np.uint8)
     drift = np.zeros(n_out, dtype=np.uint8)
     out = dict(snr=snr, harm=harm, drift=drift, mu1=mu1, sigma1=sigma1)
-    if is_degenerate(mu1, sigma1) or n_out == 0:
+    if (not tab[4] if tab is not None else is_degenerate(mu1, sigma1)) or n_out == 0:
         return out
-    mu, sig, rs, nm = tables(mu1, sigma1, H)
+    mu, sig, rs, nm = tab[:4] if tab is not None else tables(mu1, sigma1, H)
     n_end = n_r if not fundamental_end else min(n_r, int(fundamental_end))
     lib = _load()
     fn = lib.hso_2d_f64 if f64 else lib.hso_2d_f32
@@ -346,11 +355,13 @@ def candidates(snr, harm, drift, threshold, spectrum=0, bins=None):
 
 
 def hs_batched(x, offsets, H, mode, threshold, *, first_bin=1, fundamental_end=0,
-               harmonic_mask=0, precision="f32", spectra=None, dense=False):
+               harmonic_mask=0, precision="f32", spectra=None, dense=False, norm_tables=None):
     """Independent spectra ``x[offsets[s]:offsets[s+1]]``, each with its own statistics.
 
     Returns ``candidates`` (sorted by spectrum then bin) and, with ``dense``,
     the per-spectrum outputs.  ``spectra`` restricts the work to a subset.
+    ``norm_tables``: ``[n_spectra][2][H]`` caller tables (mu_k, then sigma_k)
+    instead of the statistics.
     """
     offsets = np.asarray(offsets, dtype=np.int64)
     which = range(len(offsets) - 1) if spectra is None else spectra
@@ -358,7 +369,8 @@ def hs_batched(x, offsets, H, mode, threshold, *, first_bin=1, fundamental_end=0
     for s in which:
         r = hs_1d(x[offsets[s]:offsets[s + 1]], H, mode, first_bin=first_bin,
                   fundamental_end=fundamental_end, harmonic_mask=harmonic_mask,
-                  precision=precision)
+                  precision=precision,
+                  norm_table=None if norm_tables is None else (norm_tables[s][0], norm_tables[s][1]))
         cands.append(candidates(r["snr"], r["harm"], r["drift"], threshold, spectrum=s))
         if dense:
             per[s] = r

@@ -13,23 +13,40 @@
 
 namespace {
 
-thread_local std::string g_last_error;
+// The calling thread's last failure message: a fixed buffer, so recording an
+// error never allocates (and never throws).
+thread_local char g_last_error[512];
 
 hs_status fail(hs_status s, const char *msg) {
-    g_last_error = msg;
+    snprintf(g_last_error, sizeof g_last_error, "%s", msg);
     return s;
 }
 
 hs_status fail_hip(hipError_t e, const char *where) {
-    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s", where, hipGetErrorString(e));
     return HS_ERR_HIP;
+}
+
+// Every entry point runs its body through this: no C++ exception crosses the
+// C ABI (a failed host allocation inside the library, e.g. of the graph
+// cache or the tuner's strings, becomes HS_ERR_NOMEM).
+template <class Body>
+hs_status guarded(Body &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(HS_ERR_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(HS_ERR_INTERNAL, "unexpected exception inside the library");
+    }
 }
 
 int bucket(int H) {
     if (H <= 4) return 4;
     if (H <= 8) return 8;
     if (H <= 16) return 16;
-    return 32;
+    if (H <= 32) return 32;
+    return 64;
 }
 
 // natural alignment of the stored powers
@@ -122,7 +139,7 @@ hs_status setup_xcd(hs_plan *p) {
     if (nx > hs::kMaxXcd) nx = hs::kMaxXcd;
     p->n_xcd = nx;
     int F = env_int("HS_XCD_F", 4);
-    p->xcd_f = (F == 2 || F == 4) ? F : 4;
+    p->xcd_f = (F == 1 || F == 2 || F == 4) ? F : 4;
     int per_cu = 0;
     hs_status s = resident_limit(p, p->xcd_f, &per_cu);
     if (s != HS_OK) return s;
@@ -155,6 +172,7 @@ hs_status enqueue_1d(hs_plan *p, const void *x, int64_t n_bins, const double *no
     sa.first_bin = p->desc.first_bin;
     sa.chunks = hs::kChunks1D;
     sa.user_norm = norm;
+    sa.user_table_h = norm && p->desc.norm_kind == HS_NORM_TABLE ? p->desc.harmonics : 0;
     hs_status s = run_norm(p, sa, 1, st);
     if (s != HS_OK) return s;
     hs::SumArgs a{};
@@ -210,6 +228,7 @@ hs_status enqueue_batched(hs_plan *p, const void *x, const int64_t *offsets, int
     sa.first_bin = p->desc.first_bin;
     sa.chunks = hs::kChunksBatched;
     sa.user_norm = norm;
+    sa.user_table_h = norm && p->desc.norm_kind == HS_NORM_TABLE ? p->desc.harmonics : 0;
     hs_status s = run_norm(p, sa, n_spectra, st);
     if (s != HS_OK) return s;
     hs::SumArgs a{};
@@ -265,6 +284,7 @@ hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_str
     sa.first_bin = p->desc.first_bin;
     sa.chunks = hs::kChunks2D;
     sa.user_norm = norm;
+    sa.user_table_h = norm && p->desc.norm_kind == HS_NORM_TABLE ? p->desc.harmonics : 0;
     hs_status s = run_norm(p, sa, 1, st);
     if (s != HS_OK) return s;
     hs::Sum2dArgs a{};
@@ -295,7 +315,7 @@ hs_status enqueue_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_str
     g.u_hi[1] = -z_min;
     g.budget = hs::ray_budget_for(p->ray_lds, false);
     if (g.budget > hs::kBlock * hs::kRayMaxPer) g.budget = hs::kBlock * hs::kRayMaxPer;
-    if (p->desc.kernel == HS_KERNEL_PERSISTENT && hs::ray_feasible(g)) {
+    if (p->desc.kernel == HS_KERNEL_PERSISTENT && p->hmax <= 32 && hs::ray_feasible(g)) {
         hs::Ray2dArgs ra{};
         ra.s = a;
         ra.g = g;
@@ -336,6 +356,7 @@ hs_status enqueue_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t
     sa.first_bin = p->desc.first_bin;
     sa.chunks = hs::kChunksBatched;
     sa.user_norm = norm;
+    sa.user_table_h = norm && p->desc.norm_kind == HS_NORM_TABLE ? p->desc.harmonics : 0;
     sa.il_spectra = n_spectra;
     sa.tab_t = p->tab_t;
     sa.tab_stride = p->max_groups;
@@ -470,11 +491,13 @@ hs_status dispatch(hs_plan *p, std::vector<uint64_t> &&key, hipStream_t st, Body
 }
 
 // Largest workgroups per CU of the persistent kernel with F fundamentals per
-// lane (it is compiled for at most 4 waves per SIMD, i.e. 4 workgroups of 256).
+// lane (compiled for at most 4 waves per SIMD, i.e. 4 workgroups of 256, for
+// F = 2 and 4, and at most 8 for F = 1).
 hs_status resident_limit(hs_plan *p, int F, int *per_cu) {
     hipError_t e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, F, per_cu);
     if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    if (*per_cu > 4) *per_cu = 4;
+    const int cap = F == 1 ? 8 : 4;
+    if (*per_cu > cap) *per_cu = cap;
     if (*per_cu < 1) *per_cu = 1;
     return HS_OK;
 }
@@ -489,7 +512,7 @@ hs_status set_shape(hs_plan *p, int F, int wgs_per_cu) {
         p->batched_plain = true;
         return HS_OK;
     }
-    if (F != 2 && F != 4) return fail(HS_ERR_ARG, "fundamentals per lane must be 0, 2 or 4");
+    if (F != 1 && F != 2 && F != 4) return fail(HS_ERR_ARG, "fundamentals per lane must be 0, 1, 2 or 4");
     int lim = 0;
     hs_status s = resident_limit(p, F, &lim);
     if (s != HS_OK) return s;
@@ -579,7 +602,7 @@ hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_
     const int F0 = p->batched_plain ? 0 : p->xcd_f, W0 = p->batched_plain ? 0 : p->xcd_blocks / p->n_cu;
     int bestF = F0, bestW = W0;
     float best = 3.4e38f;
-    for (int f : {0, 2, 4}) {
+    for (int f : {0, 1, 2, 4}) {
         if (f == 0 && p->desc.kernel != HS_KERNEL_AUTO) continue;
         int lim = 0;   // the plain kernel has one shape
         if (f != 0) s = resident_limit(p, f, &lim);
@@ -632,7 +655,10 @@ hs_status tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_
 
 hs_status check_desc(const hs_plan_desc &d) {
     if (d.harmonics < 1) return fail(HS_ERR_ARG, "harmonics must be >= 1");
-    if (d.harmonics > HS_MAX_HARMONICS) return fail(HS_ERR_UNSUPPORTED, "harmonics above 32 not supported");
+    if (d.harmonics > HS_MAX_HARMONICS) return fail(HS_ERR_UNSUPPORTED, "harmonics above 64 not supported");
+    if (is_presto(d.mode) && d.harmonics > 32)
+        return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums support harmonics up to 32");
+    if (d.norm_kind != HS_NORM_MU_SIGMA && d.norm_kind != HS_NORM_TABLE) return fail(HS_ERR_ARG, "bad norm_kind");
     if (d.mode != HS_STANDARD && d.mode != HS_GREEDY && !is_presto(d.mode)) return fail(HS_ERR_ARG, "bad mode");
     if (d.dtype != HS_F32 && d.dtype != HS_F16) return fail(HS_ERR_ARG, "bad dtype");
     if (d.first_bin < 1) return fail(HS_ERR_ARG, "first_bin must be >= 1");
@@ -750,269 +776,314 @@ void hs_plan_desc_init(hs_plan_desc *d) {
     d->max_spectra = 1024;
     d->threshold = 6.0f;
     d->kernel = HS_KERNEL_AUTO;
+    d->norm_kind = HS_NORM_MU_SIGMA;
 }
 
 hs_status hs_plan_workspace_bytes(const hs_plan_desc *desc, size_t *bytes) {
-    if (!desc || !bytes) return fail(HS_ERR_ARG, "null argument");
-    hs_status s = check_desc(*desc);
-    if (s != HS_OK) return s;
-    *bytes = layout(*desc).total;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!desc || !bytes) return fail(HS_ERR_ARG, "null argument");
+        hs_status s = check_desc(*desc);
+        if (s != HS_OK) return s;
+        *bytes = layout(*desc).total;
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_create(const hs_plan_desc *desc, hs_plan **plan) {
-    return create_plan(desc, nullptr, 0, plan);
+    return guarded([&]() -> hs_status {
+        return create_plan(desc, nullptr, 0, plan);
+    });
 }
 
 hs_status hs_plan_create_in(const hs_plan_desc *desc, void *workspace, size_t bytes, hs_plan **plan) {
-    if (!workspace) return fail(HS_ERR_ARG, "null workspace");
-    return create_plan(desc, workspace, bytes, plan);
+    return guarded([&]() -> hs_status {
+        if (!workspace) return fail(HS_ERR_ARG, "null workspace");
+        return create_plan(desc, workspace, bytes, plan);
+    });
 }
 
 hs_status hs_plan_destroy(hs_plan *p) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(p->device);
-    if (p->ws_owned) (void)hipFree(p->ws);
-    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-    (void)clear_graphs(p);
-    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    (void)hipSetDevice(cur);
-    delete p;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        if (p->ws_owned) (void)hipFree(p->ws);
+        for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+        (void)clear_graphs(p);
+        if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+        (void)hipSetDevice(cur);
+        delete p;
+        return HS_OK;
+    });
 }
 
 hs_status hs_sum_1d(hs_plan *p, const void *x, int64_t n_bins, const double *norm, float *snr, uint8_t *harm,
                     uint8_t *drift, float *partial, void *stream) {
-    if (!p || !x || !snr || !harm) return fail(HS_ERR_ARG, "null argument");
-    if (n_bins < 2 || n_bins >= (1ll << 30)) return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30)");
-    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
-    if (p->desc.report_mask != 0 && !partial) return fail(HS_ERR_ARG, "report_mask set but partial is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    return dispatch(p, {1, W(x), (uint64_t)n_bins, W(norm), W(snr), W(harm), W(drift), W(partial)}, st,
-                    [=](hipStream_t s) { return enqueue_1d(p, x, n_bins, norm, snr, harm, drift, partial, s); });
+    return guarded([&]() -> hs_status {
+        if (!p || !x || !snr || !harm) return fail(HS_ERR_ARG, "null argument");
+        if (!norm && p->desc.norm_kind == HS_NORM_TABLE) return fail(HS_ERR_ARG, "HS_NORM_TABLE needs the norm table");
+        if (n_bins < 2 || n_bins >= (1ll << 30)) return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30)");
+        if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
+        if (p->desc.report_mask != 0 && !partial) return fail(HS_ERR_ARG, "report_mask set but partial is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        return dispatch(p, {1, W(x), (uint64_t)n_bins, W(norm), W(snr), W(harm), W(drift), W(partial)}, st,
+                        [=](hipStream_t s) { return enqueue_1d(p, x, n_bins, norm, snr, harm, drift, partial, s); });
+    });
 }
 
 hs_status hs_sum_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra, const double *norm,
                          float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
                          unsigned long long *cand_count, void *stream) {
-    if (!p || !x || !offsets) return fail(HS_ERR_ARG, "null argument");
-    if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
-    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
-    if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
-    if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
-    if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
-    hipStream_t st = (hipStream_t)stream;
-    return dispatch(p,
-                    {2, W(x), W(offsets), (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
-                     (uint64_t)cand_capacity, W(cand_count)},
-                    st, [=](hipStream_t s) {
-                        return enqueue_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity,
-                                               cand_count, s);
-                    });
+    return guarded([&]() -> hs_status {
+        if (!p || !x || !offsets) return fail(HS_ERR_ARG, "null argument");
+        if (!norm && p->desc.norm_kind == HS_NORM_TABLE) return fail(HS_ERR_ARG, "HS_NORM_TABLE needs the norm table");
+        if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
+        if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
+        if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
+        if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
+        if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
+        hipStream_t st = (hipStream_t)stream;
+        return dispatch(p,
+                        {2, W(x), W(offsets), (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
+                         (uint64_t)cand_capacity, W(cand_count)},
+                        st, [=](hipStream_t s) {
+                            return enqueue_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity,
+                                                   cand_count, s);
+                        });
+    });
 }
 
 hs_status hs_sum_2d(hs_plan *p, const void *plane, int64_t n_r, int64_t row_stride, int32_t z_min, int32_t z_max,
                     const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
                     int64_t cand_capacity, unsigned long long *cand_count, void *stream) {
-    if (!p || !plane) return fail(HS_ERR_ARG, "null argument");
-    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "no f-fdot form of the PRESTO-style sums");
-    if (n_r < 2 || n_r >= (1ll << 30)) return fail(HS_ERR_ARG, "n_r out of range [2, 2^30)");
-    if (row_stride < n_r) return fail(HS_ERR_ARG, "row_stride < n_r");
-    if (z_max < z_min) return fail(HS_ERR_ARG, "z_max < z_min");
-    const int64_t n_z = (int64_t)z_max - z_min + 1;
-    if (n_z > 65535) return fail(HS_ERR_UNSUPPORTED, "more than 65535 rows");
-    if (!aligned_elem(plane, p->desc.dtype)) return fail(HS_ERR_ARG, "plane must be aligned to its element size");
-    if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
-    if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
-    if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
-    if (cand && n_z * n_r > 0xffffffffll) return fail(HS_ERR_UNSUPPORTED, "plane too large for 32-bit candidate bins");
-    hipStream_t st = (hipStream_t)stream;
-    return dispatch(p,
-                    {3, W(plane), (uint64_t)n_r, (uint64_t)row_stride, (uint64_t)(uint32_t)z_min,
-                     (uint64_t)(uint32_t)z_max, W(norm), W(snr), W(harm), W(drift), W(cand), (uint64_t)cand_capacity,
-                     W(cand_count)},
-                    st, [=](hipStream_t s) {
-                        return enqueue_2d(p, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand,
-                                          cand_capacity, cand_count, s);
-                    });
+    return guarded([&]() -> hs_status {
+        if (!p || !plane) return fail(HS_ERR_ARG, "null argument");
+        if (!norm && p->desc.norm_kind == HS_NORM_TABLE) return fail(HS_ERR_ARG, "HS_NORM_TABLE needs the norm table");
+        if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "no f-fdot form of the PRESTO-style sums");
+        if (n_r < 2 || n_r >= (1ll << 30)) return fail(HS_ERR_ARG, "n_r out of range [2, 2^30)");
+        if (row_stride < n_r) return fail(HS_ERR_ARG, "row_stride < n_r");
+        if (z_max < z_min) return fail(HS_ERR_ARG, "z_max < z_min");
+        const int64_t n_z = (int64_t)z_max - z_min + 1;
+        if (n_z > 65535) return fail(HS_ERR_UNSUPPORTED, "more than 65535 rows");
+        if (!aligned_elem(plane, p->desc.dtype)) return fail(HS_ERR_ARG, "plane must be aligned to its element size");
+        if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
+        if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
+        if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
+        if (cand && n_z * n_r > 0xffffffffll) return fail(HS_ERR_UNSUPPORTED, "plane too large for 32-bit candidate bins");
+        hipStream_t st = (hipStream_t)stream;
+        return dispatch(p,
+                        {3, W(plane), (uint64_t)n_r, (uint64_t)row_stride, (uint64_t)(uint32_t)z_min,
+                         (uint64_t)(uint32_t)z_max, W(norm), W(snr), W(harm), W(drift), W(cand), (uint64_t)cand_capacity,
+                         W(cand_count)},
+                        st, [=](hipStream_t s) {
+                            return enqueue_2d(p, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand,
+                                              cand_capacity, cand_count, s);
+                        });
+    });
 }
 
 hs_status hs_sum_interleaved(hs_plan *p, const void *x, int64_t n_bins, int32_t n_spectra, const double *norm,
                              float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand, int64_t cand_capacity,
                              unsigned long long *cand_count, void *stream) {
-    if (!p || !x) return fail(HS_ERR_ARG, "null argument");
-    if (p->desc.mode != HS_STANDARD && p->desc.mode != HS_GREEDY)
-        return fail(HS_ERR_UNSUPPORTED, "the interleaved layout runs the simple and greedy sums");
-    if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
-    if (n_bins < 2 || n_bins * (int64_t)n_spectra >= (1ll << 30))
-        return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30 / n_spectra)");
-    if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
-    if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
-    if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
-    if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
-    hipStream_t st = (hipStream_t)stream;
-    return dispatch(p,
-                    {4, W(x), (uint64_t)n_bins, (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
-                     (uint64_t)cand_capacity, W(cand_count)},
-                    st, [=](hipStream_t s) {
-                        return enqueue_interleaved(p, x, n_bins, n_spectra, norm, snr, harm, drift, cand,
-                                                   cand_capacity, cand_count, s);
-                    });
+    return guarded([&]() -> hs_status {
+        if (!p || !x) return fail(HS_ERR_ARG, "null argument");
+        if (p->desc.mode != HS_STANDARD && p->desc.mode != HS_GREEDY)
+            return fail(HS_ERR_UNSUPPORTED, "the interleaved layout runs the simple and greedy sums");
+        if (!norm && p->desc.norm_kind == HS_NORM_TABLE) return fail(HS_ERR_ARG, "HS_NORM_TABLE needs the norm table");
+        if (n_spectra < 1 || n_spectra > p->max_groups) return fail(HS_ERR_ARG, "n_spectra out of range");
+        if (n_bins < 2 || n_bins * (int64_t)n_spectra >= (1ll << 30))
+            return fail(HS_ERR_ARG, "n_bins out of range [2, 2^30 / n_spectra)");
+        if (!aligned_elem(x, p->desc.dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
+        if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
+        if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
+        if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
+        hipStream_t st = (hipStream_t)stream;
+        return dispatch(p,
+                        {4, W(x), (uint64_t)n_bins, (uint64_t)n_spectra, W(norm), W(snr), W(harm), W(drift), W(cand),
+                         (uint64_t)cand_capacity, W(cand_count)},
+                        st, [=](hipStream_t s) {
+                            return enqueue_interleaved(p, x, n_bins, n_spectra, norm, snr, harm, drift, cand,
+                                                       cand_capacity, cand_count, s);
+                        });
+    });
 }
 
 hs_status hs_interleave(const void *x, int64_t n_bins, int32_t n_spectra, int32_t elem_bytes, void *out,
                         void *stream) {
-    if (!x || !out) return fail(HS_ERR_ARG, "null argument");
-    if (elem_bytes != 2 && elem_bytes != 4) return fail(HS_ERR_ARG, "elem_bytes must be 2 or 4");
-    if (n_bins < 1 || n_spectra < 1 || n_spectra > 65535 * 64 || (n_bins + 63) / 64 > 0x7fffffffll)
-        return fail(HS_ERR_ARG, "sizes out of range");
-    if (((uintptr_t)x | (uintptr_t)out) & (uintptr_t)(elem_bytes - 1)) return fail(HS_ERR_ARG, "misaligned buffer");
-    const char *xb = (const char *)x, *ob = (const char *)out;
-    const int64_t bytes = n_bins * n_spectra * (int64_t)elem_bytes;
-    if (xb < ob + bytes && ob < xb + bytes) return fail(HS_ERR_ARG, "x and out overlap");
-    hipError_t e = hs::launch_interleave(x, n_bins, n_spectra, elem_bytes, out, (hipStream_t)stream);
-    if (e != hipSuccess) return fail_hip(e, "interleave kernel");
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!x || !out) return fail(HS_ERR_ARG, "null argument");
+        if (elem_bytes != 2 && elem_bytes != 4) return fail(HS_ERR_ARG, "elem_bytes must be 2 or 4");
+        if (n_bins < 1 || n_spectra < 1 || n_spectra > 65535 * 64 || (n_bins + 63) / 64 > 0x7fffffffll)
+            return fail(HS_ERR_ARG, "sizes out of range");
+        if (((uintptr_t)x | (uintptr_t)out) & (uintptr_t)(elem_bytes - 1)) return fail(HS_ERR_ARG, "misaligned buffer");
+        const char *xb = (const char *)x, *ob = (const char *)out;
+        const int64_t bytes = n_bins * n_spectra * (int64_t)elem_bytes;
+        if (xb < ob + bytes && ob < xb + bytes) return fail(HS_ERR_ARG, "x and out overlap");
+        hipError_t e = hs::launch_interleave(x, n_bins, n_spectra, elem_bytes, out, (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "interleave kernel");
+        return HS_OK;
+    });
 }
 
 hs_status hs_power_spectrum(const void *fft, int64_t n_bins, int32_t interbin, float scale, float *out, void *stream) {
-    if (!fft || !out) return fail(HS_ERR_ARG, "null argument");
-    if (n_bins < 1 || n_bins >= (1ll << 31)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^31)");
-    if (((uintptr_t)fft & 7u) || ((uintptr_t)out & 3u)) return fail(HS_ERR_ARG, "misaligned buffer");
-    if (!(scale > 0.0f) || !(scale < __builtin_inff())) return fail(HS_ERR_ARG, "scale must be positive and finite");
-    const int64_t out_n = interbin ? 2 * n_bins - 1 : n_bins;
-    const char *a = (const char *)fft, *b = (const char *)out;
-    if (a < b + 4 * out_n && b < a + 8 * n_bins) return fail(HS_ERR_ARG, "fft and out overlap");
-    // scale (pi/4)^2: the float factor rounded once, times scale in double, rounded once
-    const float f16 = (float)((M_PI * M_PI) / 16.0);
-    const float sch = (float)((double)scale * (double)f16);
-    hipError_t e = hs::launch_power(fft, n_bins, interbin != 0, scale, sch, out, (hipStream_t)stream);
-    if (e != hipSuccess) return fail_hip(e, "power-spectrum kernel");
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!fft || !out) return fail(HS_ERR_ARG, "null argument");
+        if (n_bins < 1 || n_bins >= (1ll << 31)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^31)");
+        if (((uintptr_t)fft & 7u) || ((uintptr_t)out & 3u)) return fail(HS_ERR_ARG, "misaligned buffer");
+        if (!(scale > 0.0f) || !(scale < __builtin_inff())) return fail(HS_ERR_ARG, "scale must be positive and finite");
+        const int64_t out_n = interbin ? 2 * n_bins - 1 : n_bins;
+        const char *a = (const char *)fft, *b = (const char *)out;
+        if (a < b + 4 * out_n && b < a + 8 * n_bins) return fail(HS_ERR_ARG, "fft and out overlap");
+        // scale (pi/4)^2: the float factor rounded once, times scale in double, rounded once
+        const float f16 = (float)((M_PI * M_PI) / 16.0);
+        const float sch = (float)((double)scale * (double)f16);
+        hipError_t e = hs::launch_power(fft, n_bins, interbin != 0, scale, sch, out, (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "power-spectrum kernel");
+        return HS_OK;
+    });
 }
 
 hs_status hs_cluster_peaks(const float *snr, const uint8_t *harm, const uint8_t *drift, const int64_t *offsets,
                            int64_t n_bins, int32_t n_spectra, int32_t radius, float threshold, hs_candidate *cand,
                            int64_t cand_capacity, unsigned long long *cand_count, void *stream) {
-    if (!snr || !harm || !cand_count || (!cand && cand_capacity > 0)) return fail(HS_ERR_ARG, "null argument");
-    if (cand_capacity < 0) return fail(HS_ERR_ARG, "negative capacity");
-    if (n_bins < 1 || n_bins >= (1ll << 32)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^32)");
-    if (offsets ? (n_spectra < 1 || n_spectra > 65535) : n_spectra != 1) return fail(HS_ERR_ARG, "n_spectra out of range");
-    if (radius < 0) return fail(HS_ERR_ARG, "radius < 0");
-    if (!(threshold == threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
-    if (((uintptr_t)snr & 3u)) return fail(HS_ERR_ARG, "misaligned snr");
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hs::launch_zero_u64(cand_count, st);
-    if (e != hipSuccess) return fail_hip(e, "counter reset");
-    hs::PeakArgs a{};
-    a.snr = snr;
-    a.harm = harm;
-    a.drift = drift;
-    a.offsets = offsets;
-    a.n_bins = n_bins;
-    a.radius = radius;
-    a.thr = threshold;
-    a.cand = cand;
-    a.cap = cand_capacity;
-    a.count = cand_count;
-    e = hs::launch_peaks(a, offsets ? n_spectra : 1, offsets ? (n_bins + n_spectra - 1) / n_spectra : n_bins, st);
-    if (e != hipSuccess) return fail_hip(e, "peak kernel");
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!snr || !harm || !cand_count || (!cand && cand_capacity > 0)) return fail(HS_ERR_ARG, "null argument");
+        if (cand_capacity < 0) return fail(HS_ERR_ARG, "negative capacity");
+        if (n_bins < 1 || n_bins >= (1ll << 32)) return fail(HS_ERR_ARG, "n_bins out of range [1, 2^32)");
+        if (offsets ? (n_spectra < 1 || n_spectra > 65535) : n_spectra != 1) return fail(HS_ERR_ARG, "n_spectra out of range");
+        if (radius < 0) return fail(HS_ERR_ARG, "radius < 0");
+        if (!(threshold == threshold)) return fail(HS_ERR_ARG, "threshold is NaN");
+        if (((uintptr_t)snr & 3u)) return fail(HS_ERR_ARG, "misaligned snr");
+        hipStream_t st = (hipStream_t)stream;
+        hipError_t e = hs::launch_zero_u64(cand_count, st);
+        if (e != hipSuccess) return fail_hip(e, "counter reset");
+        hs::PeakArgs a{};
+        a.snr = snr;
+        a.harm = harm;
+        a.drift = drift;
+        a.offsets = offsets;
+        a.n_bins = n_bins;
+        a.radius = radius;
+        a.thr = threshold;
+        a.cand = cand;
+        a.cap = cand_capacity;
+        a.count = cand_count;
+        e = hs::launch_peaks(a, offsets ? n_spectra : 1, offsets ? (n_bins + n_spectra - 1) / n_spectra : n_bins, st);
+        if (e != hipSuccess) return fail_hip(e, "peak kernel");
+        return HS_OK;
+    });
 }
 
 hs_status hs_get_norm(hs_plan *p, int32_t n, double *mu_sigma, float *tables, int32_t *valid, void *stream) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (n < 1 || n > p->last_groups) return fail(HS_ERR_ARG, "n exceeds the groups of the last call");
-    if (!mu_sigma && !tables && !valid) return fail(HS_ERR_ARG, "nothing to export");
-    hipError_t e = hs::launch_export_norm(p->norm, n, p->desc.harmonics, mu_sigma, tables, valid,
-                                          (hipStream_t)stream);
-    if (e != hipSuccess) return fail_hip(e, "export kernel");
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        if (n < 1 || n > p->last_groups) return fail(HS_ERR_ARG, "n exceeds the groups of the last call");
+        if (!mu_sigma && !tables && !valid) return fail(HS_ERR_ARG, "nothing to export");
+        hipError_t e = hs::launch_export_norm(p->norm, n, p->desc.harmonics, mu_sigma, tables, valid,
+                                              (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "export kernel");
+        return HS_OK;
+    });
 }
 
 hs_status hs_quantize_f16(const float *x, int64_t n, float scale, uint16_t *out, void *stream) {
-    if (!x || !out) return fail(HS_ERR_ARG, "null argument");
-    if (n < 0) return fail(HS_ERR_ARG, "n < 0");
-    if (!(scale > 0.0f) || !(scale < __builtin_inff())) return fail(HS_ERR_ARG, "scale must be positive and finite");
-    if (n == 0) return HS_OK;
-    hipError_t e = hs::launch_quantize_f16(x, n, scale, out, (hipStream_t)stream);
-    if (e != hipSuccess) return fail_hip(e, "quantise kernel");
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!x || !out) return fail(HS_ERR_ARG, "null argument");
+        if (n < 0) return fail(HS_ERR_ARG, "n < 0");
+        if (!(scale > 0.0f) || !(scale < __builtin_inff())) return fail(HS_ERR_ARG, "scale must be positive and finite");
+        if (n == 0) return HS_OK;
+        hipError_t e = hs::launch_quantize_f16(x, n, scale, out, (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "quantise kernel");
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_set_timing(hs_plan *p, int32_t enable) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    p->timing = enable != 0;
-    p->ev_used = 0;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        p->timing = enable != 0;
+        p->ev_used = 0;
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_get_timing(hs_plan *p, int32_t *calls, double *norm_ms, double *sum_ms) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i + 2 < p->ev_used; i += 3) {
-        hipError_t e = hipEventSynchronize(p->ev[i + 2]);
-        if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
-        float t01 = 0.0f, t12 = 0.0f;
-        e = hipEventElapsedTime(&t01, p->ev[i], p->ev[i + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t12, p->ev[i + 1], p->ev[i + 2]);
-        if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
-        a += t01;
-        b += t12;
-    }
-    if (calls) *calls = p->ev_used / 3;
-    if (norm_ms) *norm_ms = a;
-    if (sum_ms) *sum_ms = b;
-    p->ev_used = 0;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i + 2 < p->ev_used; i += 3) {
+            hipError_t e = hipEventSynchronize(p->ev[i + 2]);
+            if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+            float t01 = 0.0f, t12 = 0.0f;
+            e = hipEventElapsedTime(&t01, p->ev[i], p->ev[i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t12, p->ev[i + 1], p->ev[i + 2]);
+            if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+            a += t01;
+            b += t12;
+        }
+        if (calls) *calls = p->ev_used / 3;
+        if (norm_ms) *norm_ms = a;
+        if (sum_ms) *sum_ms = b;
+        p->ev_used = 0;
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_set_graph(hs_plan *p, int32_t enable) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    p->graph = enable != 0;
-    return p->graph ? HS_OK : clear_graphs(p);
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        p->graph = enable != 0;
+        return p->graph ? HS_OK : clear_graphs(p);
+    });
 }
 
 hs_status hs_plan_graph_info(hs_plan *p, int64_t *captures, int64_t *replays) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (captures) *captures = p->captures;
-    if (replays) *replays = p->replays;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        if (captures) *captures = p->captures;
+        if (replays) *replays = p->replays;
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_set_launch(hs_plan *p, int32_t fundamentals_per_lane, int32_t workgroups_per_cu) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
-    return set_shape(p, fundamentals_per_lane, workgroups_per_cu);
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
+        return set_shape(p, fundamentals_per_lane, workgroups_per_cu);
+    });
 }
 
 hs_status hs_plan_get_launch(hs_plan *p, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (fundamentals_per_lane) *fundamentals_per_lane = p->batched_plain ? 0 : p->xcd_f;
-    if (workgroups_per_cu) *workgroups_per_cu = p->batched_plain ? 0 : p->xcd_blocks / p->n_cu;
-    return HS_OK;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        if (fundamentals_per_lane) *fundamentals_per_lane = p->batched_plain ? 0 : p->xcd_f;
+        if (workgroups_per_cu) *workgroups_per_cu = p->batched_plain ? 0 : p->xcd_blocks / p->n_cu;
+        return HS_OK;
+    });
 }
 
 hs_status hs_plan_tune_batched(hs_plan *p, const void *x, const int64_t *offsets, int32_t n_spectra,
                                const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
                                int64_t cand_capacity, unsigned long long *cand_count, const char *cache_path,
                                void *stream) {
-    if (!p) return fail(HS_ERR_ARG, "null plan");
-    if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
-    if (p->timing) return fail(HS_ERR_ARG, "stage timing is enabled");
-    hipStream_t st = (hipStream_t)stream;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(st, &cs);
-    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
-    if (cs != hipStreamCaptureStatusNone) return fail(HS_ERR_ARG, "the stream is capturing");
-    const bool graph = p->graph;
-    p->graph = false;
-    hs_status s = tune_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
-                               cache_path, st);
-    p->graph = graph;
-    return s;
+    return guarded([&]() -> hs_status {
+        if (!p) return fail(HS_ERR_ARG, "null plan");
+        if (is_presto(p->desc.mode)) return fail(HS_ERR_UNSUPPORTED, "the PRESTO-style sums have no launch shape");
+        if (p->timing) return fail(HS_ERR_ARG, "stage timing is enabled");
+        hipStream_t st = (hipStream_t)stream;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+        if (cs != hipStreamCaptureStatusNone) return fail(HS_ERR_ARG, "the stream is capturing");
+        const bool graph = p->graph;
+        p->graph = false;
+        hs_status s = tune_batched(p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                                   cache_path, st);
+        p->graph = graph;
+        return s;
+    });
 }
 
 const char *hs_status_string(hs_status s) {
@@ -1022,10 +1093,11 @@ const char *hs_status_string(hs_status s) {
         case HS_ERR_UNSUPPORTED: return "unsupported";
         case HS_ERR_HIP: return "HIP runtime error";
         case HS_ERR_NOMEM: return "out of memory";
+        case HS_ERR_INTERNAL: return "internal error";
     }
     return "unknown status";
 }
 
-const char *hs_last_error(void) { return g_last_error.c_str(); }
+const char *hs_last_error(void) { return g_last_error; }
 
 }  // extern "C"

@@ -17,7 +17,7 @@ struct NormRec {
     double sigma1;     // sqrt of the population variance, rounded once
     int32_t valid;     // 0: degenerate normalisation, all outputs zero
     int32_t pad[3];
-    float2 t[HS_MAX_HARMONICS];   // (rs_k, nm_k) for k = 1..32
+    float2 t[HS_MAX_HARMONICS];   // (rs_k, nm_k) for k = 1..HS_MAX_HARMONICS
 };
 
 // Partial statistics of one chunk: exact-in-practice double-double sums.

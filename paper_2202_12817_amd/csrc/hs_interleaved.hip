@@ -266,6 +266,7 @@ hipError_t launch_sum_il(const IlArgs &a, int hmax, bool greedy, bool f16, hipSt
         case 8: return sum_il_h<8>(a, greedy, f16, grid, st);
         case 16: return sum_il_h<16>(a, greedy, f16, grid, st);
         case 32: return sum_il_h<32>(a, greedy, f16, grid, st);
+        case 64: return sum_il_h<64>(a, greedy, f16, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

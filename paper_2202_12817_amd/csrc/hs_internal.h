@@ -33,7 +33,8 @@ struct StatsArgs {
     int32_t chunks;           // chunks per group
     StatPart *parts;          // [groups][chunks]
     NormRec *norm;            // [groups]
-    const double *user_norm;  // NULL or [2 groups] (mu1, sigma1)
+    const double *user_norm;  // NULL, or [groups][2] (mu1, sigma1), or [groups][2][user_table_h] (mu_k, sigma_k)
+    int32_t user_table_h;     // 0: user_norm holds (mu1, sigma1) pairs; H: per-k tables of H entries
     int32_t il_spectra;       // interleaved layout: spectra per row (group g = spectrum g of n_bins bins)
     float2 *tab_t;            // NULL, or also write (rs_k, nm_k) of group g to tab_t[(k-1) tab_stride + g]
     int32_t tab_stride;

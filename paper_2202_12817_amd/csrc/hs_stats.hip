@@ -180,11 +180,29 @@ __global__ __launch_bounds__(64) void k_finalize(StatsArgs a) {
             s_sigma = sigma;
             s_valid = valid;
         }
-    } else if (lane == 0) {
-        double mu = a.user_norm[2 * g], sigma = a.user_norm[2 * g + 1];
-        s_mu = mu;
-        s_sigma = sigma;
-        s_valid = (__builtin_isfinite(mu) && __builtin_isfinite(sigma) && sigma > 0.0) ? 1 : 0;
+    } else if (a.user_table_h == 0) {
+        if (lane == 0) {
+            double mu = a.user_norm[2 * g], sigma = a.user_norm[2 * g + 1];
+            s_mu = mu;
+            s_sigma = sigma;
+            s_valid = (__builtin_isfinite(mu) && __builtin_isfinite(sigma) && sigma > 0.0) ? 1 : 0;
+        }
+    } else {
+        // the caller's per-k table [2][Ht] of this group: mu_1..mu_Ht, sigma_1..sigma_Ht;
+        // usable only if every entry is finite and every sigma_k positive (one 64-lane wave)
+        const int Ht = a.user_table_h;
+        const double *row = a.user_norm + (int64_t)g * 2 * Ht;
+        bool ok = true;
+        if (lane < Ht) {
+            const double m = row[lane], sg = row[Ht + lane];
+            ok = __builtin_isfinite(m) && __builtin_isfinite(sg) && sg > 0.0;
+        }
+        const bool all_ok = __ballot(!ok) == 0ull;
+        if (lane == 0) {
+            s_mu = row[0];
+            s_sigma = row[Ht];
+            s_valid = all_ok ? 1 : 0;
+        }
     }
     __syncthreads();
     NormRec *rec = a.norm + g;
@@ -197,7 +215,14 @@ __global__ __launch_bounds__(64) void k_finalize(StatsArgs a) {
     }
     if (lane < HS_MAX_HARMONICS) {
         float rs = 0.0f, nm = 0.0f;
-        if (valid) {
+        if (valid && a.user_table_h > 0) {
+            if (lane < a.user_table_h) {
+                const double *row = a.user_norm + (int64_t)g * 2 * a.user_table_h;
+                const double mu_k = row[lane], sig_k = row[a.user_table_h + lane];
+                rs = (float)(1.0 / sig_k);
+                nm = (float)(-(mu_k / sig_k));
+            }
+        } else if (valid) {
             const double k = (double)(lane + 1);
             const double mu_k = k * mu1;
             const double sig_k = sqrt_rn(k) * sigma1;

@@ -243,6 +243,7 @@ hipError_t launch_sum_1d(const SumArgs &a, int hmax, bool greedy, bool f16, dim3
         case 8: return sum1d_h<8>(a, greedy, f16, grid, st);
         case 16: return sum1d_h<16>(a, greedy, f16, grid, st);
         case 32: return sum1d_h<32>(a, greedy, f16, grid, st);
+        case 64: return sum1d_h<64>(a, greedy, f16, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -258,6 +259,7 @@ hipError_t launch_sum_2d(const Sum2dArgs &a, int hmax, bool greedy, bool f16, in
         case 8: return sum2d_h<8>(a, greedy, f16, grid, st);
         case 16: return sum2d_h<16>(a, greedy, f16, grid, st);
         case 32: return sum2d_h<32>(a, greedy, f16, grid, st);
+        case 64: return sum2d_h<64>(a, greedy, f16, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

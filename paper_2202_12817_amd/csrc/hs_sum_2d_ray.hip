@@ -181,7 +181,7 @@ __device__ __forceinline__ void walk_tile(const Ray2dArgs &a, const Tile &tl, co
                 K = qv;
             }
         }
-        float S = 0.0f, best = -__builtin_inff();   // any finite SNR beats it: the first eligible k wins
+        float S = 0.0f, best = 0.0f;                // kb == 0: no eligible k yet
         int kb = 0, db = 0;
         int32_t d = 0, T = rw.T1, D = rw.D1, kR = R;
 #pragma unroll
@@ -201,7 +201,7 @@ __device__ __forceinline__ void walk_tile(const Ray2dArgs &a, const Tile &tl, co
             const float2 tk = tab[k - 1];
             const float snr = __builtin_fmaf(S, tk.x, tk.y);
             if ((a.s.kmask >> (k - 1)) & 1ull) {
-                if (snr > best) {
+                if (kb == 0 || snr > best) {   // the first eligible k, then strict >
                     best = snr;
                     kb = k;
                     db = d;

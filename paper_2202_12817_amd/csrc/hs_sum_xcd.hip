@@ -116,7 +116,7 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
         m[f] = n[f];
         d[f] = 0;
         S[f] = 0.0f;
-        best[f] = -__builtin_inff();                       // any finite SNR beats it: first eligible k wins
+        best[f] = 0.0f;                                    // no eligible k yet (kb == 0)
         kb[f] = 0;
         db[f] = 0;
     }
@@ -155,7 +155,7 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
             S[f] = S[f] + v;                                // + 0 on inactive lanes
             if (el) {                                       // wave-uniform
                 const float snr = __builtin_fmaf(S[f], tk.x, tk.y);
-                const bool upd = act && snr > best[f];
+                const bool upd = act && (kb[f] == 0 || snr > best[f]);   // the first eligible k, then strict >
                 best[f] = upd ? snr : best[f];
                 kb[f] = upd ? k : kb[f];
                 db[f] = upd ? (int)d[f] : db[f];
@@ -216,11 +216,13 @@ __global__ __launch_bounds__(1024) void k_chunk_prefix(const int64_t *offsets, i
     if (threadIdx.x == 0) prefix[n_spectra] = carry;
 }
 
-// At most 4 waves per SIMD (4 resident workgroups per CU): lets the compiler
-// use up to 128 VGPRs, so the unrolled harmonic loop never spills (with the
-// default occupancy target it capped VGPRs at 64 and spilled to scratch).
+// Occupancy target: at most 4 waves per SIMD (4 resident workgroups per CU)
+// for F = 2 and 4, which lets the compiler use up to 128 VGPRs, so the
+// unrolled harmonic loop never spills (with the default target it capped
+// VGPRs at 64 and spilled to scratch); F = 1 needs about half the registers
+// and may run 8 workgroups per CU.
 template <int HMAX, bool GREEDY, bool F16, int F>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_sum_xcd(XcdArgs xa) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, F == 1 ? 8 : 4))) void k_sum_xcd(XcdArgs xa) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
     constexpr int CH = kBlock * F;                 // fundamentals per pass (class-0 chunk)
     const SumArgs &a = xa.s;
@@ -267,11 +269,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) 
             spec_info(si, a.offsets, a.n_bins, s, CH, a.H);
         }
         const uint32_t c = g - base;
+        // class of chunk c: the last class whose first chunk is <= c (unrolled
+        // with constant indices, so the tables stay in registers)
         int j = 0;
-        while (j + 1 < kClasses && c >= si.first[j + 1]) ++j;
-        const int64_t lo = (int64_t)si.bound[j] + (int64_t)(c - si.first[j]) * ((int64_t)CH << j);
+        uint32_t fj = si.first[0], bj = si.bound[0], bj1 = si.bound[1];
+#pragma unroll
+        for (int i = 1; i < kClasses; ++i)
+            if (c >= si.first[i]) {
+                j = i;
+                fj = si.first[i];
+                bj = si.bound[i];
+                bj1 = si.bound[i + 1];
+            }
+        const int64_t lo = (int64_t)bj + (int64_t)(c - fj) * ((int64_t)CH << j);
         int64_t hi = lo + ((int64_t)CH << j);
-        if (hi > (int64_t)si.bound[j + 1]) hi = si.bound[j + 1];
+        if (hi > (int64_t)bj1) hi = bj1;
         const NormRec *nr = a.norm + __builtin_amdgcn_readfirstlane(s);
         const int valid = nr->valid;
         if (s != tab_s) {                                      // uniform: reload the table
@@ -292,6 +304,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) 
 
 template <int HMAX, bool GREEDY, bool F16>
 const void *kernel_ptr(int F) {
+    if (F == 1) return (const void *)k_sum_xcd<HMAX, GREEDY, F16, 1>;
     return F == 2 ? (const void *)k_sum_xcd<HMAX, GREEDY, F16, 2> : (const void *)k_sum_xcd<HMAX, GREEDY, F16, 4>;
 }
 
@@ -306,7 +319,8 @@ const void *xcd_kernel(int hmax, bool greedy, bool f16, int F) {
         case 4: return kernel_ptr_h<4>(greedy, f16, F);
         case 8: return kernel_ptr_h<8>(greedy, f16, F);
         case 16: return kernel_ptr_h<16>(greedy, f16, F);
-        default: return kernel_ptr_h<32>(greedy, f16, F);
+        case 32: return kernel_ptr_h<32>(greedy, f16, F);
+        default: return kernel_ptr_h<64>(greedy, f16, F);
     }
 }
 

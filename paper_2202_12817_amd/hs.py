@@ -17,12 +17,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhs.so")
 
-HS_OK, HS_ERR_ARG, HS_ERR_UNSUPPORTED, HS_ERR_HIP, HS_ERR_NOMEM = 0, 1, 2, 3, 4
+HS_OK, HS_ERR_ARG, HS_ERR_UNSUPPORTED, HS_ERR_HIP, HS_ERR_NOMEM, HS_ERR_INTERNAL = 0, 1, 2, 3, 4, 5
 HS_STANDARD, HS_GREEDY = 0, 1
 HS_PRESTO, HS_PRESTO_ALL, HS_PRESTO_PLUS = 2, 3, 4
 HS_F32, HS_F16 = 0, 1
 HS_KERNEL_AUTO, HS_KERNEL_PERSISTENT, HS_KERNEL_PLAIN = 0, 1, 2
-HS_MAX_HARMONICS = 32
+HS_NORM_MU_SIGMA, HS_NORM_TABLE = 0, 1
+HS_MAX_HARMONICS = 64
 
 EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_create_in", "hs_plan_workspace_bytes",
             "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16",
@@ -35,7 +36,8 @@ class HsPlanDesc(ctypes.Structure):
     _fields_ = [("harmonics", ctypes.c_int32), ("mode", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("first_bin", ctypes.c_int32), ("harmonic_mask", ctypes.c_uint64),
                 ("report_mask", ctypes.c_uint64), ("fundamental_end", ctypes.c_int64),
-                ("max_spectra", ctypes.c_int32), ("threshold", ctypes.c_float), ("kernel", ctypes.c_int32)]
+                ("max_spectra", ctypes.c_int32), ("threshold", ctypes.c_float), ("kernel", ctypes.c_int32),
+                ("norm_kind", ctypes.c_int32)]
 
 
 class HsCandidate(ctypes.Structure):

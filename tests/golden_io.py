@@ -105,3 +105,28 @@ def read_peaks(name="hand_peaks.txt"):
                 keep = [tuple(int(v) for v in p.split(":")) for p in kv["keep"].split(",") if p]
                 cases.append(dict(threshold=float(kv["threshold"]), radius=int(kv["radius"]), keep=keep))
     return off, snr, harm, cases
+
+
+def read_candidates(name="hand_candidates.txt"):
+    """Powers, offsets and the hand-worked candidate cases at the threshold."""
+    offsets, values, cases = None, None, []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] == "spectra":
+                offsets = np.array(_ints(tok[1]), dtype=np.int64)
+            elif tok[0] == "values":
+                values = np.array([float(v) for v in tok[1:]], dtype=np.float32)
+            elif tok[0] == "case":
+                kv = _kv(tok[2:])
+                mask = 0 if kv["mask"] == "all" else sum(1 << (k - 1) for k in _ints(kv["mask"]))
+                recs = []
+                for r in kv["cands"].split(","):
+                    if r:
+                        s, b, h, d, v = r.split(":")
+                        recs.append((int(s), int(b), float(v), int(h), int(d)))
+                cases.append(dict(mode=tok[1], H=int(kv["H"]), mask=mask, thr=float(kv["thr"]), cands=recs))
+    return values, offsets, cases

@@ -51,11 +51,33 @@ def test_desc_defaults(lib):
     assert (d.harmonics, d.mode, d.dtype, d.first_bin) == (32, hs.HS_GREEDY, hs.HS_F32, 1)
     assert d.harmonic_mask == 0 and d.report_mask == 0 and d.fundamental_end == 0
     assert d.max_spectra == 1024 and d.threshold == pytest.approx(6.0) and d.kernel == hs.HS_KERNEL_AUTO
+    assert d.norm_kind == hs.HS_NORM_MU_SIGMA
+
+
+def test_harmonic_limits(lib):
+    # H = 1..64 for the simple and greedy sums; the PRESTO-style sums stop at 32
+    from paper_2202_12817_amd import hs
+    n = ctypes.c_size_t()
+    for mode in (hs.HS_STANDARD, hs.HS_GREEDY):
+        for H in (1, 32, 33, 48, 64):
+            d = hs.hs_plan_desc_init(mode=mode, harmonics=H, harmonic_mask=1 << (H - 1), report_mask=1 << (H - 1))
+            assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_OK, (mode, H)
+            d = hs.hs_plan_desc_init(mode=mode, harmonics=H, norm_kind=hs.HS_NORM_TABLE)
+            assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_OK, (mode, H)
+        d = hs.hs_plan_desc_init(mode=mode, harmonics=65)
+        assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
+    for mode in (hs.HS_PRESTO, hs.HS_PRESTO_ALL, hs.HS_PRESTO_PLUS):
+        d = hs.hs_plan_desc_init(mode=mode, harmonics=32)
+        assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_OK
+        d = hs.hs_plan_desc_init(mode=mode, harmonics=33)
+        assert lib.hs_plan_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
+    assert lib.hs_status_string(hs.HS_ERR_INTERNAL) == b"internal error"
 
 
 @pytest.mark.parametrize("field,value,status", [
-    ("harmonics", 0, 1), ("harmonics", 33, 2), ("mode", 7, 1), ("dtype", 5, 1), ("first_bin", 0, 1),
+    ("harmonics", 0, 1), ("harmonics", 65, 2), ("mode", 7, 1), ("dtype", 5, 1), ("first_bin", 0, 1),
     ("max_spectra", 0, 1), ("max_spectra", 70000, 1), ("fundamental_end", -1, 1), ("kernel", 3, 1),
+    ("norm_kind", 2, 1), ("norm_kind", -1, 1),
 ])
 def test_plan_create_rejects_bad_desc(lib, field, value, status):
     from paper_2202_12817_amd import hs
@@ -137,7 +159,7 @@ def test_workspace_bytes_and_caller_workspace_checks(lib):
         assert n % 256 == 0 and n > 0
         sizes.append(n)
     assert sizes == sorted(sizes) and sizes[-1] > sizes[0]
-    bad = hs.hs_plan_desc_init(harmonics=33)
+    bad = hs.hs_plan_desc_init(harmonics=65)
     n = ctypes.c_size_t()
     assert lib.hs_plan_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == hs.HS_ERR_UNSUPPORTED
     assert lib.hs_plan_workspace_bytes(None, ctypes.byref(n)) == hs.HS_ERR_ARG

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hs_oracle.c")
 PINS = ["tests/test_oracle_pipeline.py", "tests/test_oracle_golden.py", "tests/test_oracle_stats.py",
         "tests/test_oracle_bruteforce.py", "tests/test_oracle_physics.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_presto.py"]
+        "tests/test_oracle_presto.py", "tests/test_oracle_candidates.py", "tests/test_oracle_table.py"]
 
 C_MUTANTS = {
     "greedy-tie-moves": ("if (b > a) { d += 1; v = b; }", "if (b >= a) { d += 1; v = b; }"),
@@ -56,6 +56,9 @@ PY_MUTANTS = {
     "exec(src, oracle.__dict__)\n",
     "peak-window-one-sided": "import oracle, inspect\n"
     "src = inspect.getsource(oracle.cluster_peaks).replace('min(hi, n + radius + 1)', 'n + 1')\n"
+    "exec(src, oracle.__dict__)\n",
+    "candidate-at-threshold": "import oracle, inspect\n"
+    "src = inspect.getsource(oracle.candidates).replace('snr32 > np.float32(threshold)', 'snr32 >= np.float32(threshold)')\n"
     "exec(src, oracle.__dict__)\n",
     "variance-about-zero": "import oracle\n"
     "_s = oracle.stats\n"
