@@ -37,19 +37,51 @@ def _code_tokens(text):
     return "".join(text.split())
 
 
+CSRC = os.path.join(ROOT, "paper_2202_12817_amd", "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def _local_includes(path, seen):
+    """``path`` and every header it includes with quotes, recursively (found in csrc/ or include/)."""
+    if path in seen or not os.path.exists(path):
+        return
+    seen.append(path)
+    for name in re.findall(r'#include\s+"([^"]+)"', open(path).read()):
+        for d in (CSRC, INCLUDE):
+            if os.path.exists(os.path.join(d, name)):
+                _local_includes(os.path.join(d, name), seen)
+                break
+
+
 def source_hash(kernel_file="hs_sum_xcd.hip"):
     """Hash of what a kernel is compiled from (its source and the headers it
     includes, comments stripped, and the build script with its flags): a
     counter figure is valid only for the kernel it was taken from."""
     import hashlib
     h = hashlib.sha256()
-    pkg = os.path.join(ROOT, "paper_2202_12817_amd")
-    for f in (os.path.join(pkg, "csrc", kernel_file), os.path.join(pkg, "csrc", "hs_device.h"),
-              os.path.join(pkg, "csrc", "hs_internal.h"), os.path.join(ROOT, "include", "hs.h")):
+    files = []
+    _local_includes(os.path.join(CSRC, kernel_file), files)
+    for f in files:
         h.update(os.path.basename(f).encode())
         h.update(_code_tokens(open(f).read()).encode())
-    h.update(open(os.path.join(pkg, "build.py"), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2202_12817_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
+
+
+def kernel_files():
+    """Kernel name (``k_...``) -> the csrc file that defines it."""
+    out = {}
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith(".hip"):
+            for name in re.findall(r"__global__[^;{]*?\b(k_\w+)\s*\(", open(os.path.join(CSRC, f)).read()):
+                out.setdefault(name, f)
+    return out
+
+
+def short_kernel_name(full):
+    """``void hs::(anonymous namespace)::k_sum_xcd<32, true, false, 2>(hs::XcdArgs)`` -> ``k_sum_xcd<32, true, false, 2>``."""
+    m = re.search(r"\b(k_\w+)(<[^()]*>)?", full)
+    return (m.group(1) + (m.group(2) or "")) if m else None
 
 
 TABLE2_FILE = os.path.join(ROOT, "profiles", "table2_1024x131072_greedy_presto.txt")
@@ -72,85 +104,151 @@ def table2_counters():
     return out
 
 
-def read_traffic(kernel):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 summary, or None."""
-    try:
-        for line in open(TRAFFIC_FILE):
-            if line.startswith("json: "):
+def profile_records(path=None):
+    """``json:`` records of the committed counter summaries (``profiles/*.txt``)
+    whose kernel sources still hash to the recorded value, keyed by
+    (summary file name, kernel)."""
+    import glob
+    out = {}
+    files = [path] if path else sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt")))
+    for f in files:
+        try:
+            for line in open(f):
+                if not line.startswith("json: "):
+                    continue
                 rec = json.loads(line[6:])
-                if rec.get("source") == source_hash() and rec.get("kernel") == kernel:
-                    return rec["fetch_bytes"] + rec["write_bytes"]
-    except (OSError, KeyError, ValueError):
-        pass
+                kf = rec.get("file") or kernel_files().get((rec.get("kernel") or "").split("<")[0])
+                if kf and rec.get("source") == source_hash(kf):
+                    out[(os.path.basename(f), rec["kernel"])] = rec
+        except (OSError, KeyError, ValueError):
+            continue
+    return out
+
+
+def read_counters(kernel, summary=None):
+    """The newest valid counter record of ``kernel`` (from ``summary`` if given), or None."""
+    recs = profile_records(summary)
+    for (_, k), rec in sorted(recs.items()):
+        if k == kernel:
+            return rec
     return None
 
 
-def pmc_summary(dirs):
-    """Summarise rocprofv3 --pmc CSV output (FETCH_SIZE, WRITE_SIZE runs) into per-dispatch bytes.
+def read_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 summary, or None."""
+    rec = read_counters(kernel, TRAFFIC_FILE)
+    if rec and "fetch_bytes" in rec and "write_bytes" in rec:
+        return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
 
-    Each counter is scaled by what it reads for the calibration kernel (an
-    elementwise negation that reads and writes CALIB_BYTES, run in the same
-    process).  One ``json:`` line per batched FP32 greedy harmonic-sum kernel
-    found (one per launch shape profiled)."""
+
+PMC_KEYS = {"FETCH_SIZE": "fetch_bytes", "WRITE_SIZE": "write_bytes", "TCC_HIT_sum": "l2_hit",
+            "TCC_MISS_sum": "l2_miss", "TCC_REQ_sum": "l2_req", "SQ_INSTS_VALU": "valu",
+            "SQ_INSTS_VMEM_RD": "vmem_rd", "SQ_INSTS_SALU": "salu", "SQ_INSTS_LDS": "lds",
+            "SQ_WAVES": "waves", "SQ_BUSY_CYCLES": "busy_cycles", "SQ_WAVE_CYCLES": "wave_cycles"}
+
+
+def pmc_summary(dirs):
+    """Summarise rocprofv3 output directories (``--kernel-trace --stats`` runs
+    and ``--pmc`` runs, CSV) into per-dispatch figures of every harmonic-sum
+    library kernel: average duration, HBM bytes (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for the calibration kernel -- an
+    elementwise negation that reads and writes CALIB_BYTES in the same
+    process), L2 hits and misses, and instruction counts.  Ends with one
+    ``json:`` line per kernel carrying the hash of the sources it was compiled
+    from (``source``)."""
     import csv
     import glob
-    out = {}
+    per = {}
+    dur = {}
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            per = {}
             for r in csv.DictReader(open(f)):
-                key = (r["Kernel_Name"], r["Counter_Name"])
-                per.setdefault(key, []).append(float(r["Counter_Value"]))
-            for (kname, cname), vals in per.items():
-                out.setdefault(cname, {}).setdefault(kname, []).extend(vals)
-    lines = []
-    recs = {}
-    for cname, key in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
-        kern = out.get(cname, {})
-        copy = [v for k, vs in kern.items() if "neg" in k for v in vs]
+                per.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                name = r.get("Name") or r.get("KERNEL_NAME") or ""
+                calls, total = int(r.get("Calls", 0) or 0), float(r.get("TotalDurationNs", 0) or 0)
+                c0, t0 = dur.get(name, (0, 0.0))
+                dur[name] = (c0 + calls, t0 + total)
+    lines, recs = [], {}
+    scales = {}
+    for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+        copy = [v for (k, c), vs in per.items() if c == cname and "neg" in k for v in vs]
         calib = max(copy) if copy else None
-        scale = CALIB_BYTES / (calib * 1024.0) if calib else None
-        lines.append("%s: calibration copy of %d bytes reads %s KiB -> scale %s" % (
-            cname, CALIB_BYTES, "%.1f" % calib if calib else "n/a", "%.4f" % scale if scale else "n/a"))
-        for k, vs in sorted(kern.items()):
-            if "hs::" not in k:
-                continue
-            avg = sum(vs) / len(vs)
-            lines.append("  %-70s dispatches %3d  avg %12.1f KiB  scaled %14.0f bytes" % (
-                k[:70], len(vs), avg, avg * 1024.0 * (scale or 1.0)))
-            m = re.search(r"k_sum_xcd<32, true, false, (\d)>", k)
-            if m:
-                name = SUM_KERNEL % int(m.group(1))
-                recs.setdefault(name, {"kernel": name, "source": source_hash()})[key] = avg * 1024.0 * (scale or 1.0)
-    for rec in recs.values():
-        lines.append("json: " + json.dumps(rec))
+        scales[cname] = CALIB_BYTES / (calib * 1024.0) if calib else None
+        if cname in {c for (_, c) in per}:
+            lines.append("%s: calibration copy of %d bytes reads %s KiB -> scale %s" % (
+                cname, CALIB_BYTES, "%.1f" % calib if calib else "n/a",
+                "%.4f" % scales[cname] if scales[cname] else "n/a"))
+    files = kernel_files()
+
+    def rec_of(full):
+        short = short_kernel_name(full)
+        if not short or short.split("<")[0] not in files:
+            return None
+        f = files[short.split("<")[0]]
+        return recs.setdefault(short, {"kernel": short, "file": f, "source": source_hash(f)})
+
+    for (kname, cname), vs in sorted(per.items()):
+        r = rec_of(kname)
+        if r is None or cname not in PMC_KEYS:
+            continue
+        avg = sum(vs) / len(vs)
+        if cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            avg = avg * 1024.0 * (scales[cname] or 1.0)
+        r[PMC_KEYS[cname]] = avg
+        r.setdefault("dispatches", {})[cname] = len(vs)
+    for kname, (calls, total) in dur.items():
+        r = rec_of(kname)
+        if r is not None and calls:
+            r["avg_ns"] = total / calls
+            r["calls"] = calls
+    lines.append("%-36s %6s %11s %12s %12s %8s %12s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB",
+                                                       "L2_hit", "VALU"))
+    for k in sorted(recs):
+        r = recs[k]
+        hit = r.get("l2_hit")
+        miss = r.get("l2_miss")
+        lines.append("%-36s %6s %11s %12s %12s %8s %12s" % (
+            k[:36], r.get("calls", "-"), "%.1f" % (r["avg_ns"] / 1e3) if "avg_ns" in r else "-",
+            "%.1f" % (r["fetch_bytes"] / 1e6) if "fetch_bytes" in r else "-",
+            "%.1f" % (r["write_bytes"] / 1e6) if "write_bytes" in r else "-",
+            "%.1f%%" % (100.0 * hit / (hit + miss)) if hit is not None and miss is not None and hit + miss > 0 else "-",
+            "%.4g" % r["valu"] if "valu" in r else "-"))
+    for k in sorted(recs):
+        r = dict(recs[k])
+        r.pop("dispatches", None)
+        lines.append("json: " + json.dumps(r))
     return "\n".join(lines)
 
 
-def keff_sum(lengths, H, greedy, first_bin=1):
+def keff_sum(lengths, H, greedy, first_bin=1, fundamental_end=0):
     """Sum over fundamentals of the harmonics summed (exact, per the truncation rule)."""
     total = 0
     for N in lengths:
         N = int(N)
+        top = N - 1 if not fundamental_end else min(N, int(fundamental_end)) - 1
         for k in range(1, H + 1):
-            # fundamentals n >= first_bin with k (n + greedy) <= N - 1
-            hi = (N - 1) // k - (1 if greedy else 0)
+            # fundamentals first_bin <= n <= top with k (n + greedy) <= N - 1
+            hi = min((N - 1) // k - (1 if greedy else 0), top)
             if hi >= first_bin:
-                total += min(hi, N - 1) - first_bin + 1
+                total += hi - first_bin + 1
     return total
 
 
-def line_bytes_sum(lengths, H, greedy, elem, first_bin=1):
+def line_bytes_sum(lengths, H, greedy, elem, first_bin=1, fundamental_end=0):
     """Bytes moved from L2 to the CUs at cache-line granularity (128 B lines,
     waves of 64 consecutive fundamentals): a fundamental-step at harmonic k
     moves about min(k elem, 128) bytes, summed over every step."""
     total = 0
     for N in lengths:
         N = int(N)
+        top = N - 1 if not fundamental_end else min(N, int(fundamental_end)) - 1
         for k in range(1, H + 1):
-            hi = (N - 1) // k - (1 if greedy else 0)
+            hi = min((N - 1) // k - (1 if greedy else 0), top)
             if hi >= first_bin:
-                total += (min(hi, N - 1) - first_bin + 1) * min(k * elem, 128)
+                total += (hi - first_bin + 1) * min(k * elem, 128)
     return total
 
 
@@ -166,8 +264,11 @@ def keff_sum_2d(n_r, z_min, z_max, H, greedy, first_bin=1):
     return total
 
 
-def plane_2d_leg(hs, torch, dev, steps, warmup):
-    """The f-fdot plane (2^21 columns x 201 rows, z = -100..100, H = 16, dense outputs)."""
+def plane_2d_leg(hs, torch, dev, steps, warmup, error=True, kernel="auto"):
+    """The f-fdot plane (2^21 columns x 201 rows, z = -100..100, H = 16, dense
+    outputs), FP32 and FP16 storage, simple and greedy sums; with ``error`` the
+    FP16 outputs are compared with the FP32 GPU outputs on the whole plane and
+    with the float64 oracle on the original FP32 plane at sampled rows."""
     import synthetic
     plane, _ = synthetic.config4(threads=16)
     n_z, n_r = plane.shape
@@ -176,14 +277,19 @@ def plane_2d_leg(hs, torch, dev, steps, warmup):
     p16 = torch.empty(plane.shape, dtype=torch.int16, device=dev)
     scale = float(np.float32(plane.mean(dtype=np.float64)))
     hs.hs_quantize_f16(p32, plane.size, scale, p16)
-    del plane
-    snr = torch.empty((n_z, n_r), dtype=torch.float32, device=dev)
-    harm = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
-    drift = torch.empty((n_z, n_r), dtype=torch.uint8, device=dev)
-    out = {"workload": "f-fdot plane %d x %d (z = %d..%d), H=%d, dense snr/harm/drift" % (n_r, n_z, z_min, z_max, h2)}
-    for dname, dt, pin, eb in (("f32", hs.HS_F32, p32, 4), ("f16", hs.HS_F16, p16, 2)):
-        for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
-            plan = hs.Plan(harmonics=h2, mode=mode, dtype=dt)
+    outs = {}
+    for dname in ("f32", "f16"):
+        outs[dname] = (torch.empty((n_z, n_r), dtype=torch.float32, device=dev),
+                       torch.empty((n_z, n_r), dtype=torch.uint8, device=dev),
+                       torch.empty((n_z, n_r), dtype=torch.uint8, device=dev))
+    out = {"workload": "f-fdot plane %d x %d (z = %d..%d), H=%d, dense snr/harm/drift" % (n_r, n_z, z_min, z_max, h2),
+           "kernel": kernel}
+    mu_sigma = torch.zeros(2, dtype=torch.float64, device=dev)
+    for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
+        for dname, dt, pin, eb in (("f32", hs.HS_F32, p32, 4), ("f16", hs.HS_F16, p16, 2)):
+            snr, harm, drift = outs[dname]
+            plan = hs.Plan(harmonics=h2, mode=mode, dtype=dt, kernel={"auto": hs.HS_KERNEL_AUTO, "plain": hs.HS_KERNEL_PLAIN,
+                                                                     "persistent": hs.HS_KERNEL_PERSISTENT}[kernel])
             for _ in range(warmup):
                 hs.hs_sum_2d(plan.handle, pin, n_r, n_r, z_min, z_max, None, snr, harm, drift)
             torch.cuda.synchronize()
@@ -194,6 +300,9 @@ def plane_2d_leg(hs, torch, dev, steps, warmup):
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / steps
             c, nm, sm = hs.hs_plan_get_timing(plan.handle)
+            hs.hs_plan_set_timing(plan.handle, False)
+            if dname == "f32":
+                hs.hs_get_norm(plan.handle, 1, mu_sigma)
             plan.close()
             work = keff_sum_2d(n_r, z_min, z_max, h2, mode == hs.HS_GREEDY)
             comp = n_z * n_r * (eb + 6)
@@ -203,7 +312,90 @@ def plane_2d_leg(hs, torch, dev, steps, warmup):
                 "stage_ms": {"normalisation": nm / max(1, c), "harmonic_sum": sum_ms},
                 "sum_kernel_gbs_compulsory": comp / (sum_ms * 1e-3) / 1e9,
                 "sum_kernel_frac_compulsory": comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if error:
+            torch.cuda.synchronize()
+            ms = mu_sigma.cpu().numpy()
+            rows = [0, 40, 99, 100, 101, 150, 200]
+            out["f16_error_" + mname] = fp16_error_stats(
+                torch, outs["f32"], outs["f16"], 6.0,
+                sample=[(plane[i], (outs["f16"][0][i], outs["f16"][1][i], outs["f16"][2][i]),
+                         (outs["f32"][0][i], outs["f32"][1][i], outs["f32"][2][i]), i) for i in rows],
+                oracle_call=lambda row_plane, i, m=mode: plane_row_oracle(plane, z_min, z_max, h2, m, i,
+                                                                          (float(ms[0]), float(ms[1]))),
+                sample_label="plane rows %s (z = %s), float64 oracle with the FP32 plane's (mu1, sigma1)" % (
+                    rows, [z_min + i for i in rows]))
+    del plane
     return out
+
+
+def plane_row_oracle(plane, z_min, z_max, H, mode, i, norm):
+    """Float64 oracle outputs of plane row i (every column) on the FP32 plane."""
+    import oracle
+    n_r = plane.shape[1]
+    idx = np.arange(i * n_r, (i + 1) * n_r, dtype=np.int64)
+    return oracle.hs_2d(plane, z_min, z_max, H, oracle.GREEDY if mode == 1 else oracle.STANDARD, norm=norm,
+                        idx=idx, precision="f64")
+
+
+def fp16_error_stats(torch, o32, o16, thr, sample, oracle_call, sample_label):
+    """What FP16 storage costs: (a) FP16 vs FP32 GPU outputs on every bin --
+    bins whose harmonic count or drift differ (a flipped greedy comparison or
+    argmax), SNR difference on the other bins, and the candidate sets at
+    ``thr``; (b) FP16 GPU outputs vs the float64 oracle on the original FP32
+    data for ``sample`` = [(data, fp16 outputs, fp32 outputs, label)], with the
+    FP32 GPU path's own error beside it.  ``oracle_call(data, label)`` returns
+    the oracle's float64 outputs of one sample item."""
+    s32, h32, d32 = (t.reshape(-1) for t in o32)
+    s16, h16, d16 = (t.reshape(-1) for t in o16)
+    path = (h32 != h16) | (d32 != d16)
+    same = ~path
+    ds = (s16 - s32).abs() / s32.abs().clamp(min=1.0)
+    c32 = (s32 > thr) & (h32 > 0)
+    c16 = (s16 > thr) & (h16 > 0)
+    res = {"vs_fp32_gpu": {
+        "bins": int(s32.numel()),
+        "harm_diff": int((h32 != h16).sum().item()), "drift_diff": int((d32 != d16).sum().item()),
+        "harm_or_drift_diff": int(path.sum().item()),
+        "max_rel_dsnr_same_harm_drift": float(ds[same].max().item()) if bool(same.any()) else 0.0,
+        "max_rel_dsnr_all": float(ds.max().item()),
+        "candidates_fp32": int(c32.sum().item()), "candidates_fp16": int(c16.sum().item()),
+        "only_fp32": int((c32 & ~c16).sum().item()), "only_fp16": int((c16 & ~c32).sum().item()),
+        "rel": "abs(snr16 - snr32) / max(1, abs(snr32))"}}
+    del path, same, ds, c32, c16
+    agg = {"bins": 0, "max_rel_dsnr": 0.0, "max_rel_dsnr_same_harm_drift": 0.0, "harm_diff": 0, "drift_diff": 0,
+           "over_quantisation_bound": 0, "fp32_gpu_max_rel_dsnr": 0.0, "fp32_gpu_harm_or_drift_diff": 0}
+    errs = []
+    for data, g16, g32, lab in sample:
+        w = oracle_call(data, lab)
+        s64, hh, dd = w["snr"].reshape(-1), w["harm"].reshape(-1), w["drift"].reshape(-1)
+        a16 = [t.reshape(-1).cpu().numpy() for t in g16]
+        a32 = [t.reshape(-1).cpu().numpy() for t in g32]
+        e = np.abs(a16[0].astype(np.float64) - s64) / np.maximum(1.0, np.abs(s64))
+        sm = (a16[1] == hh) & (a16[2] == dd)
+        mu, sg = w["mu1"], w["sigma1"]
+        # first-order worst case of storage rounding (relative 2^-11 per value, statistics included)
+        bound = 2.0 ** -11 * (2.0 * np.sqrt(np.maximum(hh, 1)) * mu / sg + np.abs(s64) * (2.0 + 2.0 * mu * mu / (sg * sg))) \
+            + 1e-5 * np.maximum(1.0, np.abs(s64))
+        e32 = np.abs(a32[0].astype(np.float64) - s64) / np.maximum(1.0, np.abs(s64))
+        agg["bins"] += int(s64.size)
+        agg["max_rel_dsnr"] = max(agg["max_rel_dsnr"], float(e.max(initial=0.0)))
+        agg["max_rel_dsnr_same_harm_drift"] = max(agg["max_rel_dsnr_same_harm_drift"], float(e[sm].max(initial=0.0)))
+        agg["harm_diff"] += int((a16[1] != hh).sum())
+        agg["drift_diff"] += int((a16[2] != dd).sum())
+        agg["over_quantisation_bound"] += int((np.abs(a16[0].astype(np.float64) - s64) > bound).sum())
+        agg["fp32_gpu_max_rel_dsnr"] = max(agg["fp32_gpu_max_rel_dsnr"], float(e32.max(initial=0.0)))
+        agg["fp32_gpu_harm_or_drift_diff"] += int(((a32[1] != hh) | (a32[2] != dd)).sum())
+        errs.append(e)
+    if errs:
+        e = np.concatenate(errs)
+        agg["p99_rel_dsnr"] = float(np.quantile(e, 0.99))
+        agg["p999_rel_dsnr"] = float(np.quantile(e, 0.999))
+        agg["mean_rel_dsnr"] = float(e.mean())
+    agg["sample"] = sample_label
+    agg["bound"] = ("abs(dsnr) <= 2^-11 (2 sqrt(harm) mu1/sigma1 + abs(snr64) (2 + 2 mu1^2/sigma1^2)) + 1e-5 max(1, abs(snr64))"
+                    " on a path the rounding does not change")
+    res["vs_fp64_oracle_on_fp32_data"] = agg
+    return res
 
 
 # Table 2 of the paper (V100, sum kernels only, 1024 spectra of 2^17 bins):
@@ -401,6 +593,191 @@ def calibration_copy(torch, dev):
     del src, dst
 
 
+PROBE_K = 32
+PROBE_LINE_BYTES = sum(min(4 * k, 128) for k in range(1, PROBE_K + 1))   # per fundamental (waves of 64)
+PROBE_SETS = (("l2_resident", 1 << 19), ("mall_resident", 1 << 24), ("beyond_l2", 1 << 28))
+
+
+def probe_leg(torch, dev, reps=10):
+    """Gather ceilings of this device (libhs_probe.so): the greedy walk's
+    stride-k pair gather (32 harmonics, waves of 64 consecutive fundamentals,
+    no arithmetic beyond the compare) over a 2 MB set that every XCD's L2
+    holds, a 64 MB set and a 1 GB set.  Line bytes = per fundamental the sum
+    over k of min(4 k, 128) B, the L2-to-CU traffic of 128-byte lines; HIP
+    events on the launch stream, median of ``reps`` launches."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2202_12817_amd", "libhs_probe.so"))
+    lib.hsp_gather.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    lib.hsp_gather.restype = ctypes.c_int
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = 8 * n_cu
+    n_fund = 1 << 24
+    stream = torch.cuda.current_stream(dev)
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    res = {"pattern": "greedy pair gather, K=%d harmonics, %d fundamentals per launch, %d workgroups of 256"
+                      % (PROBE_K, n_fund, blocks),
+           "line_bytes_per_fundamental": PROBE_LINE_BYTES}
+    for name, n in PROBE_SETS:
+        x = torch.rand(n + 2, dtype=torch.float32, device=dev)
+
+        def call():
+            rc = lib.hsp_gather(x.data_ptr(), n - 1, n_fund, blocks, out.data_ptr(), stream.cuda_stream)
+            if rc:
+                raise RuntimeError("hsp_gather failed: %d" % rc)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            call()
+            b.record(stream)
+            ts.append((a, b))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ts]))
+        clk = n_cu * 2.4e9 * ms * 1e-3
+        res[name] = {"set_bytes": 4 * n, "ms": ms, "line_gbs": n_fund * PROBE_LINE_BYTES / (ms * 1e-3) / 1e9,
+                     "steps_per_clk_per_cu": n_fund * PROBE_K / clk,
+                     "kernel": "k_probe_gather<%d>" % ({1 << 19: 0, 1 << 24: 1, 1 << 28: 2}[n])}
+        rec = read_counters(res[name]["kernel"])
+        if rec and "fetch_bytes" in rec:
+            res[name]["fetch_gbs"] = rec["fetch_bytes"] / (ms * 1e-3) / 1e9
+            res[name]["fetch_bytes"] = rec["fetch_bytes"]
+        del x
+    del out
+    return res
+
+
+def fp16_error_batched(hs, torch, x, off, xt, x16, ot, B, stream, sample):
+    """FP16 storage error on the batched workload: dense FP32 and FP16 GPU
+    outputs of every spectrum compared bin by bin, and the FP16 outputs of the
+    ``sample`` spectra compared with the float64 oracle run on the original
+    FP32 spectra (one thread per spectrum)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    n = int(x.size)
+    o = {}
+    for name, dt, xin in (("f32", hs.HS_F32, xt), ("f16", hs.HS_F16, x16)):
+        snr = torch.empty(n, dtype=torch.float32, device=xt.device)
+        harm = torch.empty(n, dtype=torch.uint8, device=xt.device)
+        drift = torch.empty(n, dtype=torch.uint8, device=xt.device)
+        plan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=dt, max_spectra=B, threshold=THRESHOLD)
+        hs.hs_sum_batched(plan.handle, xin, ot, B, None, snr, harm, drift, None, 0, None, stream)
+        torch.cuda.synchronize()
+        plan.close()
+        o[name] = (snr, harm, drift)
+    with ThreadPoolExecutor(max(1, min(len(sample), cpu_threads()))) as ex:
+        ref = dict(zip(sample, ex.map(lambda s: oracle.hs_1d(x[off[s]:off[s + 1]], H, oracle.GREEDY, precision="f64"),
+                                      sample)))
+    items = [(s, tuple(t[int(off[s]):int(off[s + 1])] for t in o["f16"]),
+              tuple(t[int(off[s]):int(off[s + 1])] for t in o["f32"]), s) for s in sample]
+    res = fp16_error_stats(torch, o["f32"], o["f16"], THRESHOLD, items, lambda d, s: ref[s],
+                           "spectra %s (%d bins), float64 oracle on the FP32 spectra" % (
+                               list(sample), int(sum(off[s + 1] - off[s] for s in sample))))
+    del o
+    return res
+
+
+def cpu_threads():
+    """Host threads the CPU legs use: the process's CPU set, at most 16 (the
+    share of one GPU on a GPU host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_leg(x, off, lengths, sample_n, single_n, reps=3):
+    """The oracle as it stands (float mirror: exact statistics in Python, the
+    per-fundamental C loops, candidate selection) on the host: a thread pool
+    over the first ``sample_n`` spectra (the C loops release the interpreter
+    lock), wall-clock median of ``reps`` runs, and one thread on the first
+    ``single_n`` spectra."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    def one(s):
+        r = oracle.hs_1d(x[off[s]:off[s + 1]], H, oracle.GREEDY)
+        oracle.candidates(r["snr"], r["harm"], r["drift"], THRESHOLD, spectrum=s)
+
+    th = cpu_threads()
+    sample = list(range(sample_n))
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(th) as ex:
+            list(ex.map(one, sample))
+        ts.append(time.perf_counter() - t0)
+    multi = float(np.median(ts))
+    single = list(range(single_n))
+    ts1 = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for s in single:
+            one(s)
+        ts1.append(time.perf_counter() - t0)
+    one_s = float(np.median(ts1))
+    work = keff_sum(lengths[sample], H, True)
+    work1 = keff_sum(lengths[single], H, True)
+    return {"value": work / multi, "unit": "bin·harmonics/s", "cores": th, "kind": "oracle",
+            "sample": "first %d spectra of the same batch (%d bins), float mirror: exact statistics, per-fundamental "
+                      "C loops and candidate selection, one spectrum per thread, %d threads, median of %d runs"
+                      % (len(sample), int(lengths[sample].sum()), th, reps),
+            "ms_per_run": 1e3 * multi, "single_core_value": work1 / one_s,
+            "single_core_sample": "first %d spectra (%d bins), median of %d runs" % (
+                len(single), int(lengths[single].sum()), reps),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def roofline_entry(kernel, comp_bytes, line_bytes, kernel_ms, probe, traffic_file=None):
+    """Roofline of a harmonic-sum kernel: the HBM roofline of its compulsory
+    bytes (input read once, outputs written once), plus the two on-chip
+    resources the walk is bound by -- line traffic from L2 to the CUs against
+    the probe's L2-resident ceiling, and traffic fetched beyond the L2 (the
+    kernel's FETCH_SIZE from the committed counters) against the probe's
+    beyond-L2 ceiling -- and which of the three is closest to its ceiling."""
+    t = kernel_ms * 1e-3
+    ach = comp_bytes / t / 1e9
+    rec = read_counters(kernel, traffic_file)
+    traffic = rec["fetch_bytes"] + rec["write_bytes"] if rec and "fetch_bytes" in rec and "write_bytes" in rec else None
+    r = {"bound": "hbm", "kernel": kernel, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": ach / HBM_PEAK_GBS, "traffic": traffic}
+    fr = {"hbm": ach / HBM_PEAK_GBS}
+    if probe:
+        g = line_bytes / t / 1e9
+        r["gather"] = {"achieved": g, "peak": probe["l2_resident"]["line_gbs"], "unit": "GB/s",
+                       "frac": g / probe["l2_resident"]["line_gbs"],
+                       "what": "128-byte lines from L2 to the CUs (sum over steps of min(k s, 128) B) vs the "
+                               "probe's L2-resident pair gather"}
+        fr["gather"] = r["gather"]["frac"]
+        beyond = probe["beyond_l2"]
+        peak = beyond.get("fetch_gbs")
+        if rec and "fetch_bytes" in rec and peak:
+            f = rec["fetch_bytes"] / t / 1e9
+            r["fabric"] = {"achieved": f, "peak": peak, "unit": "GB/s", "frac": f / peak,
+                           "fetch_bytes": rec["fetch_bytes"],
+                           "what": "bytes fetched beyond the L2 (FETCH_SIZE, committed counters) vs the probe's "
+                                   "1 GB-set pair gather (its own FETCH_SIZE)"}
+            fr["fabric"] = r["fabric"]["frac"]
+    r["binding"] = max(fr, key=fr.get)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,18 +785,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--spectra", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the plain and FP16 legs")
-    ap.add_argument("--cpu-sample", type=int, default=72, help="spectra in the CPU oracle sample (about 10-15 s of one core)")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg but the headline step")
+    ap.add_argument("--cpu-sample", type=int, default=96, help="spectra of the threaded CPU oracle run")
+    ap.add_argument("--cpu-single", type=int, default=4, help="spectra of the one-thread CPU oracle run")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file of the tuner (default: tune afresh)")
     ap.add_argument("--launch", default=None, metavar="F,W",
                     help="fixed launch shape (fundamentals per lane, workgroups per CU) instead of tuning")
-    ap.add_argument("--plane-2d", action="store_true", help="also time the f-fdot plane (2^21 x 201, H=16)")
-    ap.add_argument("--leg", choices=["table2", "plane_2d"], default=None,
+    ap.add_argument("--no-plane", action="store_true", help="skip the f-fdot plane leg (2^21 x 201, H=16)")
+    ap.add_argument("--leg", choices=["table2", "plane_2d", "gather"], default=None,
                     help="run only this leg and print its JSON object (profiling aid)")
+    ap.add_argument("--fp16", action="store_true", help="headline step on FP16 storage (profiling aid)")
+    ap.add_argument("--plane-kernel", choices=["auto", "plain", "persistent"], default="auto",
+                    help="kernel choice of the plane leg (profiling aid)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a 1 GiB read + 1 GiB write elementwise kernel (reference for rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
-                    help="summarise rocprofv3 --pmc CSV directories and exit (no GPU work)")
+                    help="summarise rocprofv3 output directories (kernel trace and --pmc CSV) and exit (no GPU work)")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(args.pmc_summary))
@@ -439,7 +820,9 @@ def main():
         if args.calibration_copy:
             calibration_copy(torch, dev)
         legs = {"table2": lambda: table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup),
-                "plane_2d": lambda: plane_2d_leg(hs, torch, dev, args.steps, args.warmup)}
+                "plane_2d": lambda: plane_2d_leg(hs, torch, dev, args.steps, args.warmup, error=False,
+                                                 kernel=args.plane_kernel),
+                "gather": lambda: probe_leg(torch, dev)}
         print(json.dumps({args.leg: legs[args.leg]()}))
         return
     x, off = synthetic.config3(n_spectra=args.spectra, threads=16)
@@ -449,58 +832,74 @@ def main():
     ot = torch.from_numpy(off).to(dev)
     B = args.spectra
     work = keff_sum(lengths, H, True)
+    stream = torch.cuda.current_stream(dev)
+    x16 = None
+    if args.fp16 or not args.no_extra:
+        # FP16 storage with a per-spectrum scale (the spectrum's mean)
+        x16 = torch.empty(n_bins, dtype=torch.int16, device=dev)
+        for s in range(B):
+            scale = float(np.float32(x[off[s]:off[s + 1]].mean(dtype=np.float64)))
+            hs.hs_quantize_f16(xt.data_ptr() + 4 * int(off[s]), int(lengths[s]), scale,
+                               x16.data_ptr() + 2 * int(off[s]), stream)
+        torch.cuda.synchronize()
 
-    plan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, max_spectra=B, threshold=THRESHOLD)
     cap = 1 << 24
     cand = torch.empty((cap, 4), dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream(dev)
 
     def step(p, xin):
         hs.hs_sum_batched(p.handle, xin, ot, B, None, None, None, None, cand, cap, count, stream)
 
-    # launch shape of the persistent kernel: tuned on this batch (the tuner
-    # times every shape; results do not depend on it)
-    if args.launch:
-        hs.hs_plan_set_launch(plan.handle, *[int(v) for v in args.launch.split(",")])
-    else:
-        hs.hs_plan_tune_batched(plan.handle, xt, ot, B, None, None, None, None, cand, cap, count, args.tune_cache,
-                                stream)
-    shape = hs.hs_plan_get_launch(plan.handle)
-    for _ in range(args.warmup):
-        step(plan, xt)
-    torch.cuda.synchronize()
-    hs.hs_plan_set_timing(plan.handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(plan, xt)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    calls, norm_ms, sum_ms = hs.hs_plan_get_timing(plan.handle)
-    hs.hs_plan_set_timing(plan.handle, False)
-    n_cand = int(count.item())
-    # the same step replayed as one captured hipGraph per call
-    hs.hs_plan_set_graph(plan.handle, True)
-    step(plan, xt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(plan, xt)
-    torch.cuda.synchronize()
-    graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    graph_info = hs.hs_plan_graph_info(plan.handle)
-    hs.hs_plan_set_graph(plan.handle, False)
-    ms_step = 1e3 * elapsed / args.steps
-    value = work * args.steps / elapsed
+    def timed(dtype, xin, fundamental_end=0, graph=False):
+        """Tune the launch shape on this batch (unless fixed), warm up, time the steps."""
+        plan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=dtype, max_spectra=B, threshold=THRESHOLD,
+                       fundamental_end=fundamental_end)
+        if args.launch:
+            hs.hs_plan_set_launch(plan.handle, *[int(v) for v in args.launch.split(",")])
+        else:
+            hs.hs_plan_tune_batched(plan.handle, xin, ot, B, None, None, None, None, cand, cap, count,
+                                    args.tune_cache, stream)
+        shape = hs.hs_plan_get_launch(plan.handle)
+        for _ in range(args.warmup):
+            step(plan, xin)
+        torch.cuda.synchronize()
+        hs.hs_plan_set_timing(plan.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(plan, xin)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        calls, norm_ms, sum_ms = hs.hs_plan_get_timing(plan.handle)
+        hs.hs_plan_set_timing(plan.handle, False)
+        r = {"elapsed": elapsed, "shape": shape, "norm_ms": norm_ms / max(1, calls),
+             "sum_ms": sum_ms / max(1, calls), "candidates": int(count.item())}
+        if graph:
+            # the same step replayed as one captured hipGraph per call
+            hs.hs_plan_set_graph(plan.handle, True)
+            step(plan, xin)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step(plan, xin)
+            torch.cuda.synchronize()
+            r["graph_ms"] = 1e3 * (time.perf_counter() - t0) / args.steps
+            r["graph_info"] = hs.hs_plan_graph_info(plan.handle)
+            hs.hs_plan_set_graph(plan.handle, False)
+        plan.close()
+        return r
 
-    in_bytes = 4 * n_bins
-    lines = line_bytes_sum(lengths, H, True, 4)
-    sum_kernel = SUM_KERNEL % shape[0] if shape[0] else "k_sum_1d<32, true, false>"
+    eb = 2 if args.fp16 else 4
+    head = timed(hs.HS_F16 if args.fp16 else hs.HS_F32, x16 if args.fp16 else xt, graph=not args.no_extra)
+    ms_step = 1e3 * head["elapsed"] / args.steps
+    value = work * args.steps / head["elapsed"]
+    shape = head["shape"]
+    n_cand = head["candidates"]
+    in_bytes = eb * n_bins
+    lines = line_bytes_sum(lengths, H, True, eb)
+    sum_kernel = ("k_sum_xcd<32, true, %s, %d>" % ("true" if args.fp16 else "false", shape[0])) if shape[0] else \
+        "k_sum_1d<32, true, %s>" % ("true" if args.fp16 else "false")
     cand_bytes = 16 * min(n_cand, cap)
-    sum_avg_ms = sum_ms / max(1, calls)
-    norm_avg_ms = norm_ms / max(1, calls)
-    achieved = (in_bytes + cand_bytes) / (sum_avg_ms * 1e-3) / 1e9
+    probe = None if args.no_extra else probe_leg(torch, dev)
 
     result = {
         "metric": "spectral bins·harmonics/sec and achieved HBM GB/s (% of peak), plain vs batched/FP16",
@@ -513,33 +912,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16 storage, f32 sums" if args.fp16 else "f32",
         "data": "synthetic",
-        "config": {"workload": "batched 1D greedy harmonic sum: %d spectra of 2^20..2^22 FP32 bins "
+        "config": {"workload": "batched 1D greedy harmonic sum: %d spectra of 2^20..2^22 %s bins "
                                "(Exp(1) noise + 5 pulse trains each), H=%d, SNR>%g candidate compaction"
-                               % (B, H, THRESHOLD),
+                               % (B, "FP16" if args.fp16 else "FP32", H, THRESHOLD),
                    "spectra": B, "bins": n_bins, "H": H, "mode": "greedy", "threshold": THRESHOLD,
                    "bin_harmonics": work, "candidates": n_cand},
-        "bins_per_s": n_bins * args.steps / elapsed,
+        "bins_per_s": n_bins * args.steps / head["elapsed"],
         "hbm_gbs_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9,
         "hbm_frac_compulsory": (in_bytes + cand_bytes) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "stage_ms": {"normalisation": norm_avg_ms, "harmonic_sum": sum_avg_ms},
+        "stage_ms": {"normalisation": head["norm_ms"], "harmonic_sum": head["sum_ms"]},
         "launch": {"fundamentals_per_lane": shape[0], "workgroups_per_cu": shape[1], "tuned": not args.launch},
-        "graph_replay": {"ms_per_step": graph_ms, "value": work / (graph_ms * 1e-3),
-                         "graphs_recorded": graph_info[0], "replays": graph_info[1]},
-        "gather": {"touched_bytes": 8 * work, "touched_gbs": 8 * work / (sum_avg_ms * 1e-3) / 1e9,
-                   "l2_to_cu_bytes": lines, "l2_to_cu_tbs": lines / (sum_avg_ms * 1e-3) / 1e12,
-                   "note": "harmonic-sum kernel: 8 B touched per greedy step (the compared pair); "
-                           "min(4 k, 128) B per step at cache-line granularity"},
-        "roofline": {"bound": "hbm", "kernel": sum_kernel, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic(sum_kernel)},
+        "gather": {"touched_bytes": 2 * eb * work, "touched_gbs": 2 * eb * work / (head["sum_ms"] * 1e-3) / 1e9,
+                   "l2_to_cu_bytes": lines, "l2_to_cu_tbs": lines / (head["sum_ms"] * 1e-3) / 1e12,
+                   "note": "harmonic-sum kernel: 2 s B touched per greedy step (the compared pair); "
+                           "min(k s, 128) B per step at cache-line granularity"},
+        "roofline": roofline_entry(sum_kernel, in_bytes + cand_bytes, lines, head["sum_ms"], probe, TRAFFIC_FILE),
     }
+    if "graph_ms" in head:
+        result["graph_replay"] = {"ms_per_step": head["graph_ms"], "value": work / (head["graph_ms"] * 1e-3),
+                                  "graphs_recorded": head["graph_info"][0], "replays": head["graph_info"][1]}
+    if probe:
+        result["gather_ceilings"] = probe
 
     if args.calibration_copy:
         calibration_copy(torch, dev)
 
     if not args.no_extra:
+        # full-H fundamentals only (reading of the truncation rule: fundamentals
+        # below (N-1)/(H+1) of the shortest spectrum, all 32 harmonics each)
+        n_hi = (int(lengths.min()) - 1) // (H + 1)
+        fh = timed(hs.HS_F32, xt, fundamental_end=n_hi)
+        ms_fh = 1e3 * fh["elapsed"] / args.steps
+        work_fh = keff_sum(lengths, H, True, fundamental_end=n_hi)
+        lines_fh = line_bytes_sum(lengths, H, True, 4, fundamental_end=n_hi)
+        result["full_h_fundamentals"] = {
+            "fundamental_end": n_hi, "value": work_fh / (ms_fh * 1e-3), "unit": "bin·harmonics/s",
+            "ms_per_step": ms_fh, "stage_ms": {"normalisation": fh["norm_ms"], "harmonic_sum": fh["sum_ms"]},
+            "bin_harmonics": work_fh, "l2_to_cu_bytes": lines_fh,
+            "l2_to_cu_tbs": lines_fh / (fh["sum_ms"] * 1e-3) / 1e12, "candidates": fh["candidates"],
+            "launch": {"fundamentals_per_lane": fh["shape"][0], "workgroups_per_cu": fh["shape"][1]},
+            "note": "fundamentals [1, %d) of every spectrum (all of them sum 32 harmonics); the statistics "
+                    "still cover whole spectra" % n_hi}
+
         # plain: one hs_sum_1d per spectrum, dense outputs, no graph
         pplan = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F32, threshold=THRESHOLD,
                         kernel=hs.HS_KERNEL_PLAIN)
@@ -562,59 +978,36 @@ def main():
         torch.cuda.synchronize()
         plain_s = (time.perf_counter() - t0) / reps
         pplan.close()
+        del snr, harm, drift
         result["plain_fp32"] = {"value": work / plain_s, "ms_per_step": 1e3 * plain_s,
                                 "speedup_batched": plain_s / (ms_step * 1e-3)}
-        # FP16 storage with a per-spectrum scale
-        x16 = torch.empty(n_bins, dtype=torch.int16, device=dev)
-        for s in range(B):
-            scale = float(np.float32(x[off[s]:off[s + 1]].mean(dtype=np.float64)))
-            hs.hs_quantize_f16(base + 4 * int(off[s]), int(lengths[s]), scale, x16.data_ptr() + 2 * int(off[s]),
-                               stream)
-        plan16 = hs.Plan(harmonics=H, mode=hs.HS_GREEDY, dtype=hs.HS_F16, max_spectra=B, threshold=THRESHOLD)
-        if not args.launch:
-            hs.hs_plan_tune_batched(plan16.handle, x16, ot, B, None, None, None, None, cand, cap, count,
-                                    args.tune_cache, stream)
-        shape16 = hs.hs_plan_get_launch(plan16.handle)
-        for _ in range(args.warmup):
-            step(plan16, x16)
-        torch.cuda.synchronize()
-        hs.hs_plan_set_timing(plan16.handle, True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step(plan16, x16)
-        torch.cuda.synchronize()
-        e16 = (time.perf_counter() - t0) / args.steps
-        c16, n16, s16 = hs.hs_plan_get_timing(plan16.handle)
-        n_cand16 = int(count.item())
-        plan16.close()
-        result["batched_fp16"] = {"value": work / e16, "ms_per_step": 1e3 * e16,
-                                  "speedup_vs_plain_fp32": plain_s / e16,
-                                  "hbm_gbs_compulsory": (2 * n_bins + 16 * n_cand16) / e16 / 1e9,
-                                  "stage_ms": {"normalisation": n16 / max(1, c16), "harmonic_sum": s16 / max(1, c16)},
-                                  "launch": {"fundamentals_per_lane": shape16[0], "workgroups_per_cu": shape16[1]},
-                                  "candidates": n_cand16}
-        del x16
+        # FP16 storage, the same step
+        h16 = timed(hs.HS_F16, x16)
+        e16 = h16["elapsed"] / args.steps
+        k16 = ("k_sum_xcd<32, true, true, %d>" % h16["shape"][0]) if h16["shape"][0] else "k_sum_1d<32, true, true>"
+        n_cand16 = h16["candidates"]
+        result["batched_fp16"] = {
+            "value": work / e16, "ms_per_step": 1e3 * e16, "speedup_vs_plain_fp32": plain_s / e16,
+            "speedup_vs_batched_fp32": ms_step / (1e3 * e16),
+            "hbm_gbs_compulsory": (2 * n_bins + 16 * n_cand16) / e16 / 1e9,
+            "stage_ms": {"normalisation": h16["norm_ms"], "harmonic_sum": h16["sum_ms"]},
+            "launch": {"fundamentals_per_lane": h16["shape"][0], "workgroups_per_cu": h16["shape"][1]},
+            "candidates": n_cand16,
+            "roofline": roofline_entry(k16, 2 * n_bins + 16 * n_cand16, line_bytes_sum(lengths, H, True, 2),
+                                       h16["sum_ms"], probe),
+            "error": fp16_error_batched(hs, torch, x, off, xt, x16, ot, B, stream,
+                                        sample=[0, 1, 128, 255, 384, 511][:max(1, min(6, B))] if B > 1 else [0])}
 
-    if args.plane_2d:
+    if x16 is not None:
+        del x16
+    if not args.no_extra and not args.no_plane:
         result["plane_2d"] = plane_2d_leg(hs, torch, dev, args.steps, args.warmup)
     if not args.no_extra:
         result["small_1d"] = small_1d_leg(hs, torch, dev)
         result["table2"] = table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup)
 
     if not args.no_cpu_baseline:
-        import oracle
-        sample = list(range(min(args.cpu_sample, B)))
-        t0 = time.perf_counter()
-        for s in sample:
-            r = oracle.hs_1d(x[off[s]:off[s + 1]], H, oracle.GREEDY)
-            oracle.candidates(r["snr"], r["harm"], r["drift"], THRESHOLD, spectrum=s)
-        cpu_s = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": keff_sum(lengths[sample], H, True) / cpu_s, "unit": "bin·harmonics/s",
-                                  "cores": 1, "kind": "oracle",
-                                  "sample": "first %d spectra of the same batch (%d bins), float mirror, "
-                                            "exact statistics + per-fundamental C loops, one thread"
-                                            % (len(sample), int(lengths[sample].sum()))}
-    plan.close()
+        result["cpu_baseline"] = cpu_baseline_leg(x, off, lengths, min(args.cpu_sample, B), min(args.cpu_single, B))
     print(json.dumps(result))
 
 

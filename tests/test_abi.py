@@ -1,4 +1,6 @@
-"""The C-ABI library loads and exports every entry point of include/hs.h.
+"""The C-ABI libraries load and export every entry point their headers
+declare: libhs.so for include/hs.h, libhs_probe.so (the gather-ceiling probe
+of the benchmark) for include/hs_probe.h.
 
 No compute call is made here (no GPU in this environment): only symbol
 presence and the argument checks that return before any HIP call.
@@ -37,6 +39,23 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(hs.EXPORTED)
     for name in names:
         assert hasattr(lib, name), name
+
+
+def test_probe_library_exports_its_header():
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "hs_probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(hsp_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["hsp_gather"]
+    probe = ctypes.CDLL(os.path.join(ROOT, "paper_2202_12817_amd", "libhs_probe.so"))
+    for name in names:
+        assert hasattr(probe, name), name
+    f = probe.hsp_gather
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    # argument checks return before any HIP call: null pointers, a set that is no power of two or too large
+    assert f(None, 1023, 64, 1, None, None) != 0
+    assert f(8, 1000, 64, 1, 8, None) != 0
+    assert f(8, (1 << 28), 64, 1, 8, None) != 0
+    assert f(8, 1023, 0, 1, 8, None) != 0
 
 
 def test_struct_layouts_match_header():
