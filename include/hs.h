@@ -287,6 +287,25 @@ hs_status hs_cluster_peaks(const float *snr, const uint8_t *harm, const uint8_t 
                            void *stream);
 
 /*
+ * hs_sum_batched without a plan, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same launch sequence and kernels as hs_sum_batched with a plan made
+ * from *desc (persistent kernel, default launch shape; the same results bit
+ * for bit), with its workspace in a static device array of the library
+ * (4 MiB per device, held until the process ends) instead of plan memory.
+ * Nothing is allocated, on the host or the device.  Arguments as for
+ * hs_sum_batched; desc->max_spectra is ignored and n_spectra must be
+ * 1..1024 (HS_ERR_ARG beyond).  Every call on one device shares that array:
+ * each call clears what must start at zero, and calls that overlap on one GPU
+ * (different streams, or host threads) race on it -- enqueue them on one
+ * stream.  hs_get_norm does not apply (no plan).
+ */
+hs_status hs_sum_batched_static(const hs_plan_desc *desc, const void *x, const int64_t *offsets, int32_t n_spectra,
+                                const double *norm, float *snr, uint8_t *harm, uint8_t *drift,
+                                hs_candidate *cand, int64_t cand_capacity,
+                                unsigned long long *cand_count, void *stream);
+
+/*
  * Export the normalisation used by the most recent sum call on this plan
  * (stream-ordered device-to-device copy of its first n entries).
  *   mu_sigma  [2 n] doubles (mu1, sigma1; with HS_NORM_TABLE mu_1 and

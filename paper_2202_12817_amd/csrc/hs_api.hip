@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -759,6 +760,32 @@ hs_status create_plan(const hs_plan_desc *desc, void *workspace, size_t bytes, h
     return HS_OK;
 }
 
+// Allocation-free batched sum: the workspace of hs_sum_batched_static is this
+// file-scope device array instead of a plan's hipMalloc.  Each device holds
+// its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name is a
+// host-side stand-in).
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int kScratchMaxSpectra = 1024;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kScratchDevices];
+
+// The device address of `scratch` on device dev (current), looked up once.
+hs_status scratch_of(int dev, char **out) {
+    if (dev < 0 || dev >= kScratchDevices) return fail(HS_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1083,6 +1110,51 @@ hs_status hs_plan_tune_batched(hs_plan *p, const void *x, const int64_t *offsets
                                    cache_path, st);
         p->graph = graph;
         return s;
+    });
+}
+
+hs_status hs_sum_batched_static(const hs_plan_desc *desc, const void *x, const int64_t *offsets, int32_t n_spectra,
+                                const double *norm, float *snr, uint8_t *harm, uint8_t *drift, hs_candidate *cand,
+                                int64_t cand_capacity, unsigned long long *cand_count, void *stream) {
+    return guarded([&]() -> hs_status {
+        if (!desc || !x || !offsets) return fail(HS_ERR_ARG, "null argument");
+        hs_status cs = check_desc(*desc);
+        if (cs != HS_OK) return cs;
+        if (!norm && desc->norm_kind == HS_NORM_TABLE) return fail(HS_ERR_ARG, "HS_NORM_TABLE needs the norm table");
+        if (n_spectra < 1 || n_spectra > kScratchMaxSpectra)
+            return fail(HS_ERR_ARG, "n_spectra out of range [1, 1024] of the allocation-free call");
+        if (!aligned_elem(x, desc->dtype)) return fail(HS_ERR_ARG, "x must be aligned to its element size");
+        if (!snr && !cand) return fail(HS_ERR_ARG, "neither dense outputs nor candidates requested");
+        if (snr && !harm) return fail(HS_ERR_ARG, "snr given without harm");
+        if (cand && (!cand_count || cand_capacity < 0)) return fail(HS_ERR_ARG, "candidate buffer needs a counter");
+        hs_plan_desc d = *desc;
+        d.max_spectra = n_spectra;
+        const Layout l = layout(d);
+        if (l.total > kScratchBytes) return fail(HS_ERR_ARG, "workspace of this call exceeds the 4 MiB scratch");
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+        char *ws = nullptr;
+        hs_status s = scratch_of(dev, &ws);
+        if (s != HS_OK) return s;
+        hs_plan p{};                     // on the stack: no graph cache, no timing events, nothing allocated
+        p.desc = d;
+        p.device = dev;
+        p.hmax = bucket(d.harmonics);
+        p.max_groups = n_spectra;
+        p.parts_cap = l.parts_cap;
+        p.ws = ws;
+        p.ws_owned = false;
+        p.norm = (hs::NormRec *)(ws + l.norm);
+        p.parts = (hs::StatPart *)(ws + l.parts);
+        p.tickets = (uint32_t *)(ws + l.tickets);
+        p.prefix = (uint32_t *)(ws + l.prefix);
+        p.ray = (hs::RayBand *)(ws + l.ray);
+        p.tab_t = (float2 *)(ws + l.tab_t);
+        s = setup_xcd(&p);
+        if (s != HS_OK) return s;
+        return enqueue_batched(&p, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                               (hipStream_t)stream);
     });
 }
 

@@ -29,7 +29,8 @@ EXPORTED = ["hs_plan_desc_init", "hs_plan_create", "hs_plan_create_in", "hs_plan
             "hs_plan_destroy", "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16",
             "hs_plan_set_timing", "hs_plan_get_timing", "hs_plan_set_graph", "hs_plan_graph_info",
             "hs_plan_set_launch", "hs_plan_get_launch", "hs_plan_tune_batched", "hs_status_string",
-            "hs_last_error", "hs_sum_interleaved", "hs_interleave", "hs_power_spectrum", "hs_cluster_peaks"]
+            "hs_last_error", "hs_sum_interleaved", "hs_interleave", "hs_power_spectrum", "hs_cluster_peaks",
+            "hs_sum_batched_static"]
 
 
 class HsPlanDesc(ctypes.Structure):
@@ -74,6 +75,8 @@ def load(path: str = LIB_PATH):
         lib.hs_sum_1d.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
         lib.hs_sum_batched.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         lib.hs_sum_2d.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        lib.hs_sum_batched_static.argtypes = [ctypes.POINTER(HsPlanDesc), vp, vp, i32, vp, vp, vp, vp, vp, i64, vp,
+                                              vp]
         lib.hs_get_norm.argtypes = [vp, i32, vp, vp, vp, vp]
         lib.hs_sum_interleaved.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         lib.hs_interleave.argtypes = [vp, i64, i32, i32, vp, vp]
@@ -95,7 +98,7 @@ def load(path: str = LIB_PATH):
                      "hs_sum_1d", "hs_sum_batched", "hs_sum_2d", "hs_get_norm", "hs_quantize_f16", "hs_plan_set_timing", "hs_plan_get_timing",
                      "hs_plan_set_graph", "hs_plan_graph_info", "hs_plan_set_launch", "hs_plan_get_launch",
                      "hs_plan_tune_batched", "hs_sum_interleaved", "hs_interleave", "hs_power_spectrum",
-                     "hs_cluster_peaks"):
+                     "hs_cluster_peaks", "hs_sum_batched_static"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -171,6 +174,13 @@ def hs_sum_batched(plan, x, offsets, n_spectra, norm, snr, harm, drift, cand, ca
     _check(load().hs_sum_batched(plan, _p(x), _p(offsets), int(n_spectra), _p(norm), _p(snr), _p(harm),
                                  _p(drift), _p(cand), int(cand_capacity), _p(cand_count), _stream(stream)),
            "hs_sum_batched")
+
+
+def hs_sum_batched_static(desc, x, offsets, n_spectra, norm, snr, harm, drift, cand, cand_capacity, cand_count,
+                          stream=None):
+    _check(load().hs_sum_batched_static(ctypes.byref(desc), _p(x), _p(offsets), int(n_spectra), _p(norm), _p(snr),
+                                        _p(harm), _p(drift), _p(cand), int(cand_capacity), _p(cand_count),
+                                        _stream(stream)), "hs_sum_batched_static")
 
 
 def hs_sum_2d(plan, plane, n_r, row_stride, z_min, z_max, norm, snr, harm, drift, cand=None, cand_capacity=0,

@@ -58,6 +58,22 @@ def test_probe_library_exports_its_header():
     assert f(8, 1023, 0, 1, 8, None) != 0
 
 
+def test_static_entry_rejects_on_the_host(lib):
+    from paper_2202_12817_amd import hs
+    d = hs.hs_plan_desc_init()
+    for n in (0, 1025):
+        with pytest.raises(hs.HsError) as e:
+            hs.hs_sum_batched_static(d, 16, 16, n, None, 16, 16, None, None, 0, None, stream=0)
+        assert e.value.status == hs.HS_ERR_ARG
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_sum_batched_static(hs.hs_plan_desc_init(harmonics=65), 16, 16, 1, None, 16, 16, None, None, 0, None,
+                                 stream=0)
+    assert e.value.status == hs.HS_ERR_UNSUPPORTED
+    with pytest.raises(hs.HsError) as e:
+        hs.hs_sum_batched_static(d, 16, 16, 1, None, None, None, None, None, 0, None, stream=0)
+    assert e.value.status == hs.HS_ERR_ARG
+
+
 def test_struct_layouts_match_header():
     from paper_2202_12817_amd import hs
     assert ctypes.sizeof(hs.HsCandidate) == 16
