@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 H = 32
 THRESHOLD = 6.0
 SUM_KERNEL = "k_sum_xcd<32, true, false, %d>"         # dominant kernel (FP32 greedy; fundamentals per lane)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sum_xcd_batched_512x_h32_greedy_f32.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_512x_h32_greedy_k_sum_xcd.txt")
 CALIB_BYTES = 1 << 30
 
 
@@ -91,16 +91,20 @@ VALU_PEAK = 256 * 2.4e9      # wave instructions per second: 256 CUs, one VALU w
 def table2_counters():
     """Per-kernel counters (VALU instructions, HBM-side bytes per dispatch) of the
     Table 2 workload from the committed rocprofv3 summary, for the kernels whose
-    sources still match."""
+    sources still match, keyed by (algorithm, H)."""
     out = {}
-    try:
-        for line in open(TABLE2_FILE):
-            if line.startswith("json: "):
-                rec = json.loads(line[6:])
-                if rec.get("source") == source_hash(rec.get("file", "")):
-                    out[(rec["algorithm"], rec["H"])] = rec
-    except (OSError, KeyError, ValueError):
-        pass
+    names = {2: "presto", 3: "presto_all", 4: "presto_plus"}
+    for (_, kern), rec in profile_records(TABLE2_FILE).items():
+        m = re.match(r"k_(sum_1d|sum_xcd|presto)<(\d+), (\w+), (\w+)", kern)
+        if not m:
+            continue
+        H = int(m.group(2))
+        if m.group(1) == "presto":
+            algo = names.get(int(m.group(3)))
+        else:
+            algo = "greedy" if m.group(3) == "true" and m.group(4) == "false" else None
+        if algo:
+            out[(algo, H)] = rec
     return out
 
 

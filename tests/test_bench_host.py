@@ -48,12 +48,40 @@ def test_pmc_summary_scales_by_the_calibration_copy(tmp_path):
 
 
 def test_table2_counters_follow_the_sources(tmp_path, monkeypatch):
-    good = {"algorithm": "presto", "H": 32, "kernel": "k_presto<32, 2, false>", "file": "hs_presto.hip",
+    good = {"kernel": "k_presto<32, 2, false>", "file": "hs_presto.hip",
             "source": bench.source_hash("hs_presto.hip"), "valu": 1.0, "fetch_bytes": 2.0, "write_bytes": 3.0}
-    stale = dict(good, algorithm="presto_all", source="0000000000000000")
+    greedy = dict(good, kernel="k_sum_1d<16, true, false>", file="hs_sum.hip", source=bench.source_hash("hs_sum.hip"))
+    stale = dict(good, kernel="k_presto<32, 3, false>", source="0000000000000000")
     f = tmp_path / "t2.txt"
-    f.write_text("# summary\njson: %s\njson: %s\n" % (json.dumps(good), json.dumps(stale)))
+    f.write_text("# summary\njson: %s\njson: %s\njson: %s\n" % (json.dumps(good), json.dumps(stale), json.dumps(greedy)))
     monkeypatch.setattr(bench, "TABLE2_FILE", str(f))
     c = bench.table2_counters()
-    assert list(c) == [("presto", 32)]
+    assert sorted(c) == [("greedy", 16), ("presto", 32)]
 
+
+def test_work_and_line_counts_follow_the_truncation_rule():
+    # greedy: fundamental n sums min(H, (N-1)//(n+1)) harmonics; fundamental_end bounds n
+    N, H = 1000, 8
+    want = sum(min(H, (N - 1) // (n + 1)) for n in range(1, N))
+    assert bench.keff_sum([N], H, True) == want
+    want_end = sum(min(H, (N - 1) // (n + 1)) for n in range(1, 100))
+    assert bench.keff_sum([N], H, True, fundamental_end=100) == want_end
+    lines = sum(min(4 * k, 128) for n in range(1, N) for k in range(1, min(H, (N - 1) // (n + 1)) + 1))
+    assert bench.line_bytes_sum([N], H, True, 4) == lines
+
+
+def test_kernel_trace_durations_are_summarised(tmp_path):
+    d = tmp_path / "trace"
+    d.mkdir()
+    with open(d / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs"])
+        w.writerow(["void hs::(anonymous namespace)::k_sum_xcd<32, true, false, 4>(hs::XcdArgs)", 4, 40000000, 10000000])
+    out = bench.pmc_summary([str(d)])
+    recs = [json.loads(l[6:]) for l in out.splitlines() if l.startswith("json: ")]
+    assert len(recs) == 1 and recs[0]["kernel"] == "k_sum_xcd<32, true, false, 4>"
+    assert recs[0]["avg_ns"] == pytest.approx(1e7) and recs[0]["calls"] == 4
+
+
+def test_cpu_threads_within_the_host_share():
+    assert 1 <= bench.cpu_threads() <= 16
