@@ -560,6 +560,42 @@ def interleaved_leg(hs, torch, xt, ot, B, N, snr, harm, steps, warmup, stream):
     return res
 
 
+def single_spectrum_leg(hs, torch, dev, steps, copies=32):
+    """One long spectrum (2^22 FP32 bins, Exp(1) noise + 50 pulse trains with
+    fundamentals below N/32, H = 32), simple and greedy sums, dense outputs
+    (6 B per bin): hs_sum_1d per call (the plain kernel, the single-spectrum
+    default), cycling over `copies` copies of the input and outputs (32 x 40
+    MiB, twice the 256 MB MALL) so every call starts from HBM; HIP events on
+    the launch stream."""
+    import synthetic
+    x, _ = synthetic.config2()
+    n = int(x.size)
+    xs = torch.from_numpy(x).to(dev).repeat(copies, 1)
+    snr = torch.empty((copies, n), dtype=torch.float32, device=dev)
+    harm = torch.empty((copies, n), dtype=torch.uint8, device=dev)
+    drift = torch.empty((copies, n), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "one spectrum of %d FP32 bins, H=32, dense snr/harm/drift, %d rotating copies" % (n, copies)}
+    for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
+        plan = hs.Plan(harmonics=H, mode=mode, dtype=hs.HS_F32)
+        i = [0]
+
+        def call():
+            c = i[0] % copies
+            i[0] += 1
+            hs.hs_sum_1d(plan.handle, xs[c], n, None, snr[c], harm[c], drift[c], None, stream)
+        ms = _event_ms(torch, stream, call, max(steps, copies))
+        plan.close()
+        comp = 10.0 * n
+        work = keff_sum([n], H, mode == hs.HS_GREEDY)
+        out[mname] = {"ms_per_call": ms, "value": work / (ms * 1e-3), "unit": "bin·harmonics/s",
+                      "gbin_s": n / (ms * 1e-3) / 1e9, "hbm_gbs_compulsory": comp / (ms * 1e-3) / 1e9,
+                      "hbm_frac_compulsory": comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "l2_to_cu_tbs": line_bytes_sum([n], H, mode == hs.HS_GREEDY, 4) / (ms * 1e-3) / 1e12}
+    del xs, snr, harm, drift
+    return out
+
+
 def small_1d_leg(hs, torch, dev):
     """Call latency of a small spectrum (65536 FP32 bins, H = 8, greedy, dense
     outputs): six launches per call, replayed as one captured graph or not."""
@@ -796,7 +832,7 @@ def main():
     ap.add_argument("--launch", default=None, metavar="F,W",
                     help="fixed launch shape (fundamentals per lane, workgroups per CU) instead of tuning")
     ap.add_argument("--no-plane", action="store_true", help="skip the f-fdot plane leg (2^21 x 201, H=16)")
-    ap.add_argument("--leg", choices=["table2", "plane_2d", "gather"], default=None,
+    ap.add_argument("--leg", choices=["table2", "plane_2d", "gather", "single"], default=None,
                     help="run only this leg and print its JSON object (profiling aid)")
     ap.add_argument("--fp16", action="store_true", help="headline step on FP16 storage (profiling aid)")
     ap.add_argument("--plane-kernel", choices=["auto", "plain", "persistent"], default="auto",
@@ -826,7 +862,8 @@ def main():
         legs = {"table2": lambda: table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup),
                 "plane_2d": lambda: plane_2d_leg(hs, torch, dev, args.steps, args.warmup, error=False,
                                                  kernel=args.plane_kernel),
-                "gather": lambda: probe_leg(torch, dev)}
+                "gather": lambda: probe_leg(torch, dev),
+                "single": lambda: single_spectrum_leg(hs, torch, dev, args.steps)}
         print(json.dumps({args.leg: legs[args.leg]()}))
         return
     x, off = synthetic.config3(n_spectra=args.spectra, threads=16)
@@ -1007,6 +1044,7 @@ def main():
     if not args.no_extra and not args.no_plane:
         result["plane_2d"] = plane_2d_leg(hs, torch, dev, args.steps, args.warmup)
     if not args.no_extra:
+        result["single_spectrum"] = single_spectrum_leg(hs, torch, dev, args.steps)
         result["small_1d"] = small_1d_leg(hs, torch, dev)
         result["table2"] = table2_leg(hs, torch, dev, min(args.steps, 10), args.warmup)
 
