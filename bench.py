@@ -88,26 +88,6 @@ TABLE2_FILE = os.path.join(ROOT, "profiles", "table2_1024x131072_greedy_presto.t
 VALU_PEAK = 256 * 2.4e9      # wave instructions per second: 256 CUs, one VALU wave instruction per clock
 
 
-def table2_counters():
-    """Per-kernel counters (VALU instructions, HBM-side bytes per dispatch) of the
-    Table 2 workload from the committed rocprofv3 summary, for the kernels whose
-    sources still match, keyed by (algorithm, H)."""
-    out = {}
-    names = {2: "presto", 3: "presto_all", 4: "presto_plus"}
-    for (_, kern), rec in profile_records(TABLE2_FILE).items():
-        m = re.match(r"k_(sum_1d|sum_xcd|presto)<(\d+), (\w+), (\w+)", kern)
-        if not m:
-            continue
-        H = int(m.group(2))
-        if m.group(1) == "presto":
-            algo = names.get(int(m.group(3)))
-        else:
-            algo = "greedy" if m.group(3) == "true" and m.group(4) == "false" else None
-        if algo:
-            out[(algo, H)] = rec
-    return out
-
-
 def profile_records(path=None):
     """``json:`` records of the committed counter summaries (``profiles/*.txt``)
     whose kernel sources still hash to the recorded value, keyed by
@@ -425,7 +405,7 @@ def table2_leg(hs, torch, dev, steps, warmup):
     out = {"workload": "%d spectra of %d FP32 bins (Exp(1) noise + 5 pulse trains each), dense snr/harm"
                        % (B, n_bins // B),
            "unit": "Gbin/s (all bins / harmonic-sum kernel time)", "paper_v100_gbin_s": PAPER_TABLE2_GBINS}
-    counters = table2_counters()
+    counters = profile_records(TABLE2_FILE)
     modes = (("greedy", hs.HS_GREEDY), ("presto", hs.HS_PRESTO), ("presto_all", hs.HS_PRESTO_ALL),
              ("presto_plus", hs.HS_PRESTO_PLUS))
     for mname, mode in modes:
@@ -434,6 +414,10 @@ def table2_leg(hs, torch, dev, steps, warmup):
             plan = hs.Plan(harmonics=h, mode=mode, dtype=hs.HS_F32, max_spectra=B)
             if mode == hs.HS_GREEDY:
                 hs.hs_plan_tune_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, None, stream)
+                fl = hs.hs_plan_get_launch(plan.handle)[0]
+                kern = "k_sum_xcd<%d, true, false, %d>" % (h, fl) if fl else "k_sum_1d<%d, true, false>" % h
+            else:
+                kern = "k_presto<%d, %d, false>" % (h, mode)
             for _ in range(warmup):
                 hs.hs_sum_batched(plan.handle, xt, ot, B, None, snr, harm, None, None, 0, None, stream)
             torch.cuda.synchronize()
@@ -451,9 +435,10 @@ def table2_leg(hs, torch, dev, steps, warmup):
                  "normalisation_ms": nm / max(1, c), "call_ms": 1e3 * el,
                  "gbin_s_whole_call": n_bins / el / 1e9,
                  "sum_kernel_gbs_compulsory": comp / (sum_ms * 1e-3) / 1e9}
-            rec = counters.get((mname, h))
+            rec = counters.get((os.path.basename(TABLE2_FILE), kern))
+            r["kernel"] = kern
             hbm_frac = comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-            if rec:
+            if rec and "valu" in rec and "fetch_bytes" in rec and "write_bytes" in rec:
                 valu_rate = rec["valu"] / (sum_ms * 1e-3)
                 alu = valu_rate / VALU_PEAK > hbm_frac
                 r["roofline"] = {"bound": "alu" if alu else "hbm", "kernel": rec["kernel"],

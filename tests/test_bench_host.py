@@ -47,16 +47,16 @@ def test_pmc_summary_scales_by_the_calibration_copy(tmp_path):
     assert r["write_bytes"] == pytest.approx(10.0 * 1024)
 
 
-def test_table2_counters_follow_the_sources(tmp_path, monkeypatch):
+def test_profile_records_follow_the_sources(tmp_path):
     good = {"kernel": "k_presto<32, 2, false>", "file": "hs_presto.hip",
             "source": bench.source_hash("hs_presto.hip"), "valu": 1.0, "fetch_bytes": 2.0, "write_bytes": 3.0}
     greedy = dict(good, kernel="k_sum_1d<16, true, false>", file="hs_sum.hip", source=bench.source_hash("hs_sum.hip"))
     stale = dict(good, kernel="k_presto<32, 3, false>", source="0000000000000000")
     f = tmp_path / "t2.txt"
     f.write_text("# summary\njson: %s\njson: %s\njson: %s\n" % (json.dumps(good), json.dumps(stale), json.dumps(greedy)))
-    monkeypatch.setattr(bench, "TABLE2_FILE", str(f))
-    c = bench.table2_counters()
-    assert sorted(c) == [("greedy", 16), ("presto", 32)]
+    recs = bench.profile_records(str(f))
+    assert sorted(k for _, k in recs) == ["k_presto<32, 2, false>", "k_sum_1d<16, true, false>"]
+    assert bench.read_counters("k_presto<32, 3, false>", str(f)) is None
 
 
 def test_work_and_line_counts_follow_the_truncation_rule():
