@@ -85,30 +85,27 @@ __device__ __forceinline__ int keff(int64_t n, int64_t len, int64_t first_bin, i
 // the whole kernel on one address).
 constexpr int kStage = 256;
 
-// One pass: kBlock * F consecutive fundamentals starting at p0 (lane owns
-// p0 + f kBlock + threadIdx.x), restricted to [p0, p_end).
+// Harmonic walk of a pass with a bound per lane: each lane sums its own
+// K = min(H, (len - 1) / (n + greedy)) harmonics (0 outside [first_bin,
+// n_end)); the loop runs to the wave's largest K, lanes past their own K
+// load at an out-of-range offset (zero, no memory access) and commit nothing.
 template <int HMAX, bool GREEDY, bool F16, int F>
-__device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInfo &si, int64_t p0, int64_t p_end,
-                                          __amdgpu_buffer_rsrc_t rsrc, const float2 *tab, int valid,
-                                          Stage &st) {
+__device__ __forceinline__ void walk_lanes(const SumArgs &a, int64_t len, int64_t n_end, int64_t p0, int wave,
+                                           __amdgpu_buffer_rsrc_t rsrc, const float2 *tab, int valid,
+                                           const uint32_t (&n)[F], float (&bs)[F], int (&kbo)[F], int (&dbo)[F]) {
     using L = Loader<F16>;
     constexpr uint32_t eb = L::kBytes;
-    const int wave = threadIdx.x >> 6;
-    const int64_t len = si.len;
-    int64_t n_end = a.n_end < len ? a.n_end : len;
-    if (p_end < n_end) n_end = p_end;
     int K[F];
-    uint32_t n[F], m[F], d[F];
+    uint32_t m[F], d[F];
     float S[F], best[F];
     int kb[F], db[F];
     int KW = 0;                                             // wave-uniform loop bound
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int64_t n0 = p0 + f * kBlock;                 // first fundamental of this f-slice
-        n[f] = (uint32_t)(n0 + threadIdx.x);
         K[f] = valid ? keff<GREEDY>(n0 + threadIdx.x, len, a.first_bin, n_end, a.H) : 0;
         // K is non-increasing in n: the wave's largest K is at its first fundamental >= first_bin
-        int64_t nw = n0 + wave * 64;
+        int64_t nw = n0 + (int64_t)wave * 64;
         if (nw < a.first_bin) nw = a.first_bin;
         const int kw = valid ? keff<GREEDY>(nw, len, a.first_bin, n_end, a.H) : 0;
         KW = kw > KW ? kw : KW;
@@ -198,11 +195,135 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
     }
 #pragma unroll
     for (int f = 0; f < F; ++f) {
+        bs[f] = kb[f] ? best[f] : 0.0f;
+        kbo[f] = kb[f];
+        dbo[f] = db[f];
+    }
+}
+
+// Harmonic walk of a pass in which every lane of the wave, in all F slices,
+// is a fundamental with the same harmonic count KU and every k <= KU is
+// eligible (the common case: K changes only near len / k, and a wave holds
+// 64 consecutive fundamentals).  No bound or eligibility test per lane is
+// needed: every step loads, selects and updates.  The greedy walk keeps one
+// index per fundamental, md = k n + d (the left element of harmonic k's
+// pair), advanced by n + up; the drift at the best harmonic comes from the
+// index after that step, d = md' - (kb + 1) n.  Same sums, same SNRs, same
+// comparisons as the walk with a bound per lane.
+template <int HMAX, bool GREEDY, bool F16, int F>
+__device__ __forceinline__ void walk_uniform(int KU, __amdgpu_buffer_rsrc_t rsrc, const float2 *tab,
+                                             const uint32_t (&n)[F], float (&bs)[F], int (&kbo)[F], int (&dbo)[F]) {
+    constexpr uint32_t eb = Loader<F16>::kBytes;
+    uint32_t md[F], mdb[F];
+    float S[F], best[F];
+    int kb[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        md[f] = n[f];
+        mdb[f] = 0;
+        S[f] = 0.0f;
+        best[f] = 0.0f;
+        kb[f] = 0;
+    }
+#pragma unroll
+    for (int k = 1; k <= HMAX; ++k) {
+        if (k > KU) break;                                  // wave-uniform
+        const float2 tk = tab[k - 1];
+        float v[F];
+        uint32_t nx[F];
+        if constexpr (F16) {
+            // all slices' loads first, then their use (F loads of the wave in flight)
+            uint32_t w[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if constexpr (GREEDY)   // both halves with one 4-byte load
+                    w[f] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(md[f] * eb), 0, 0);
+                else
+                    w[f] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)(md[f] * eb), 0, 0);
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const float x0 = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[f] & 0xFFFFu));
+                if constexpr (GREEDY) {
+                    const float x1 = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[f] >> 16));
+                    const bool up = x1 > x0;
+                    v[f] = up ? x1 : x0;
+                    nx[f] = md[f] + n[f] + (up ? 1u : 0u);
+                } else {
+                    v[f] = x0;
+                    nx[f] = md[f] + n[f];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if constexpr (GREEDY) {
+                    const f32x2_t p =
+                        __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)(md[f] * eb), 0, 0));
+                    const bool up = p.y > p.x;
+                    v[f] = up ? p.y : p.x;
+                    nx[f] = md[f] + n[f] + (up ? 1u : 0u);
+                } else {
+                    v[f] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)(md[f] * eb), 0, 0));
+                    nx[f] = md[f] + n[f];
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            S[f] = S[f] + v[f];
+            const float snr = __builtin_fmaf(S[f], tk.x, tk.y);
+            const bool upd = k == 1 || snr > best[f];      // the first eligible k, then strict >
+            best[f] = upd ? snr : best[f];
+            kb[f] = upd ? k : kb[f];
+            if constexpr (GREEDY) mdb[f] = upd ? nx[f] : mdb[f];
+            md[f] = nx[f];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        bs[f] = kb[f] ? best[f] : 0.0f;
+        kbo[f] = kb[f];
+        dbo[f] = (GREEDY && kb[f]) ? (int)(mdb[f] - (uint32_t)(kb[f] + 1) * n[f]) : 0;
+    }
+}
+
+// One pass: kBlock * F consecutive fundamentals starting at p0 (lane owns
+// p0 + f kBlock + threadIdx.x), restricted to [p0, p_end).  The wave takes
+// the uniform walk when its first and last fundamental (K is non-increasing
+// in n) have the same harmonic count, it holds no bin outside [first_bin,
+// n_end) and the eligibility mask covers harmonics 1..K; else the walk with
+// a bound per lane.  The tests use wave-uniform values only (scalar code).
+template <int HMAX, bool GREEDY, bool F16, int F>
+__device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInfo &si, int64_t p0, int64_t p_end,
+                                          __amdgpu_buffer_rsrc_t rsrc, const float2 *tab, int valid,
+                                          Stage &st) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t len = si.len;
+    int64_t n_end = a.n_end < len ? a.n_end : len;
+    if (p_end < n_end) n_end = p_end;
+    uint32_t n[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) n[f] = (uint32_t)(p0 + f * kBlock + threadIdx.x);
+    int KU = 0;
+    const int64_t wf = p0 + (int64_t)wave * 64, wl = wf + (F - 1) * kBlock + 63;
+    if (valid && wf >= a.first_bin && wl < n_end) {
+        KU = keff<GREEDY>(wf, len, a.first_bin, n_end, a.H);
+        const uint64_t need = KU >= 64 ? ~0ull : (1ull << KU) - 1ull;
+        if (KU != keff<GREEDY>(wl, len, a.first_bin, n_end, a.H) || (a.kmask & need) != need) KU = 0;
+    }
+    float bs[F];
+    int kb[F], db[F];
+    if (KU > 0)
+        walk_uniform<HMAX, GREEDY, F16, F>(KU, rsrc, tab, n, bs, kb, db);
+    else
+        walk_lanes<HMAX, GREEDY, F16, F>(a, len, n_end, p0, wave, rsrc, tab, valid, n, bs, kb, db);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
         const bool in = (int64_t)n[f] < p_end;
-        const float bs = kb[f] ? best[f] : 0.0f;
         if (in) {
             const int64_t o = si.off + n[f];
-            if (a.snr) a.snr[o] = bs;
+            if (a.snr) a.snr[o] = bs[f];
             if (a.harm) a.harm[o] = (uint8_t)kb[f];
             if (a.drift) a.drift[o] = (uint8_t)db[f];
         }
@@ -210,10 +331,10 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
             hs_candidate r;
             r.spectrum = (uint32_t)s;
             r.bin = n[f];
-            r.snr = bs;
+            r.snr = bs[f];
             r.harm = (uint16_t)kb[f];
             r.drift = (uint16_t)db[f];
-            stage_push<kStage>(st, a.cand, a.cap, a.count, in && kb[f] > 0 && bs > a.thr, r);
+            stage_push<kStage>(st, a.cand, a.cap, a.count, in && kb[f] > 0 && bs[f] > a.thr, r);
         }
     }
 }
