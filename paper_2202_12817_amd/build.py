@@ -18,10 +18,11 @@ PROBE_SOURCES = ["hs_probe.hip"]
 
 # -ffp-contract=off: every float operation is the single rounding written in
 # the source (the SNR's fma is explicit).  Packed FP32 instructions are
-# disabled on the device.
+# disabled on the device.  -Wno-pass-failed: an unroll request the compiler
+# declines (large harmonic buckets) leaves a correct loop.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function"]
+         "-Wall", "-Wno-unused-function", "-Wno-pass-failed"]
 
 
 def _run(cmd):

@@ -171,6 +171,44 @@ struct Loader<true> {
     __device__ static float2 two(__amdgpu_buffer_rsrc_t r, uint32_t e) { return ld_f16x2(r, e); }
 };
 
+// Normalisation tables are written by an earlier launch and only read by
+// the sum kernels: reading them through the constant address space lets the
+// compiler use scalar loads for wave-uniform indices, even in kernels that
+// store to global memory (through a generic pointer it must assume the
+// stores may alias the table and falls back to vector loads).
+typedef __attribute__((address_space(4))) const float ctab_t;
+__device__ __forceinline__ const ctab_t *const_table(const float2 *p) { return (const ctab_t *)p; }
+// (rs_k, nm_k) of harmonic k of such a table
+__device__ __forceinline__ float2 tab_at(const ctab_t *t, int k) { return make_float2(t[2 * k - 2], t[2 * k - 1]); }
+
+// Harmonic counts from thresholds held one per lane.  K(n) = min(cap,
+// (len - 1) / (n + greedy)) is the number of k <= cap with n <= T(k), where
+// T(k) = (len - 1) / k - greedy decreases in k; lane j of every wave keeps
+// T(j + 1) (-1 for j >= cap), computed once per spectrum (cap <= 64 = lanes
+// of a wave), so the count of a wave-uniform n is the population of one
+// ballot.  Every lane of the wave must be active when these are called.
+template <bool GREEDY>
+__device__ __forceinline__ int32_t k_threshold(int64_t len, int cap) {
+    const int j = (int)(threadIdx.x & 63);
+    if (j >= cap || len < 2) return -1;
+    return (int32_t)((uint32_t)(len - 1) / (uint32_t)(j + 1)) - (GREEDY ? 1 : 0);   // len < 2^30
+}
+
+// Harmonics summed by every fundamental in [wf, wl] (wave-uniform, wl < 2^30)
+// when they agree and all of them are eligible, else 0 (the caller then
+// takes its walk with a bound per lane).  K is non-increasing in n, so the
+// two ends decide.
+__device__ __forceinline__ int uniform_k(int32_t thr, int64_t wf, int64_t wl, int64_t first_bin, int64_t n_end,
+                                         uint64_t kmask) {
+    // 32-bit compares (scalar): positions are below 2^30
+    if ((uint32_t)wf < (uint32_t)first_bin || (uint32_t)wl >= (uint32_t)n_end) return 0;
+    const int kf = __builtin_popcountll(__ballot(thr >= (int32_t)wf));
+    const int kl = __builtin_popcountll(__ballot(thr >= (int32_t)wl));
+    if (kf != kl || kf == 0) return 0;
+    const uint64_t need = kf >= 64 ? ~0ull : (1ull << kf) - 1ull;
+    return (kmask & need) == need ? kf : 0;
+}
+
 // Result of one fundamental.
 struct Best {
     float snr;

@@ -20,7 +20,7 @@ namespace {
 // Harmonic walk of fundamental n of one spectrum (descriptor r); K harmonics.
 // REPORT: also store S_k for the k in report_mask (slot-major, stride pstride).
 template <int HMAX, bool GREEDY, bool F16, bool REPORT>
-__device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K, const float2 *__restrict__ tab,
+__device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K, const ctab_t *tab,
                                      uint64_t kmask, uint64_t report_mask, float *partial, int64_t pstride) {
     using L = Loader<F16>;
     float S = 0.0f, best = 0.0f;
@@ -40,7 +40,7 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
             v = L::one(r, m);
         }
         S = S + v;
-        const float2 t = tab[k - 1];
+        const float2 t = tab_at(tab, k);
         const float snr = __builtin_fmaf(S, t.x, t.y);
         if constexpr (REPORT) {
             if ((report_mask >> (k - 1)) & 1ull) {
@@ -58,6 +58,72 @@ __device__ __forceinline__ Best walk(__amdgpu_buffer_rsrc_t r, uint32_t n, int K
         m += n;
     }
     return Best{kb ? best : 0.0f, kb, db};
+}
+
+// C consecutive harmonics k..k+C-1 of a simple sum: all C loads first, then
+// their updates in harmonic order.
+template <int C, bool F16, class RowOf, class Upd>
+__device__ __forceinline__ void simple_block(int k, uint32_t &md, uint32_t n, RowOf &row, Upd &update) {
+    float v[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = Loader<F16>::one(row(k + j), md + (uint32_t)j * n);
+#pragma unroll
+    for (int j = 0; j < C; ++j) update(k + j, v[j], 0u);
+    md += (uint32_t)C * n;
+}
+
+// Walk of a fundamental whose wave sums the same number of harmonics KU on
+// every lane, all of them eligible (the common case: K changes only where
+// (len - 1) / (n + greedy) crosses an integer, and a wave holds 64
+// consecutive fundamentals).  No per-lane bound or eligibility test: every
+// step loads, selects and updates.  The greedy walk keeps one index per
+// fundamental, md = k n + d (the left element of harmonic k's pair, in the
+// row row(k) reads), advanced by n + up; the drift at the best harmonic
+// comes from the index after that step, d = md' - (kb + 1) n.  Same sums,
+// SNRs and comparisons as walk().
+template <int HMAX, bool GREEDY, bool F16, class RowOf>
+__device__ __forceinline__ Best walk_uniform(uint32_t n, int KU, const ctab_t *tab, RowOf row) {
+    using L = Loader<F16>;
+    float S = 0.0f, best = 0.0f;
+    int kb = 0;
+    uint32_t md = n, mdb = 0;
+    auto update = [&](int k, float v, uint32_t nx) {
+        S = S + v;
+        const float2 t = tab_at(tab, k);
+        const float snr = __builtin_fmaf(S, t.x, t.y);
+        const bool upd = k == 1 || snr > best;              // the first eligible k, then strict >
+        best = upd ? snr : best;
+        kb = upd ? k : kb;
+        if constexpr (GREEDY) mdb = upd ? nx : mdb;
+    };
+    if constexpr (GREEDY) {
+#pragma unroll
+        for (int k = 1; k <= HMAX; ++k) {
+            if (k > KU) break;                              // wave-uniform
+            const float2 p = L::two(row(k), md);
+            const bool up = p.y > p.x;
+            const uint32_t nx = md + n + (up ? 1u : 0u);
+            update(k, up ? p.y : p.x, nx);
+            md = nx;
+        }
+    } else {
+        // the reads do not depend on the data: groups of four harmonics are
+        // loaded together (one basic block, four loads in flight), then the
+        // one to three left over, again together
+        int k = 1;
+        while (k + 3 <= KU) {                               // wave-uniform
+            simple_block<4, F16>(k, md, n, row, update);
+            k += 4;
+        }
+        const int r = KU - k + 1;
+        if (r == 3)
+            simple_block<3, F16>(k, md, n, row, update);
+        else if (r == 2)
+            simple_block<2, F16>(k, md, n, row, update);
+        else if (r == 1)
+            simple_block<1, F16>(k, md, n, row, update);
+    }
+    return Best{kb ? best : 0.0f, kb, (GREEDY && kb) ? (int)(mdb - (uint32_t)(kb + 1) * n) : 0};
 }
 
 // Candidate records staged per wave in LDS before one global atomic per
@@ -82,21 +148,30 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     }
     const NormRec *nr = a.norm + s;
     const int valid = nr->valid;
-    const float2 *tab = nr->t;
+    const ctab_t *tab = const_table(nr->t);
     const char *base = (const char *)a.x + off * eb;
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(base, (uint32_t)(len * eb));
     const int64_t n_end = a.n_end < len ? a.n_end : len;
-    for (int64_t t = bx; t * kBlock < len; t += gridDim.x) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int32_t thr = k_threshold<GREEDY>(len, a.H);
+    // tiles past n_end hold no fundamental: only dense outputs need them (zeros)
+    const int64_t t_lim = (a.snr || a.harm || a.drift || a.partial) ? len : n_end;
+    for (int64_t t = bx; t * kBlock < t_lim; t += gridDim.x) {
         const int64_t n = t * kBlock + threadIdx.x;
         const bool in = n < len;
+        const int KU = (valid && a.partial == nullptr)
+                           ? uniform_k(thr, t * kBlock + w * 64, t * kBlock + w * 64 + 63, a.first_bin, n_end, a.kmask)
+                           : 0;
+        Best b;
         int K = 0;
-        if (in && valid && n >= a.first_bin && n < n_end) {
+        if (KU == 0 && in && valid && n >= a.first_bin && n < n_end) {
             // 32-bit: len < 2^30
             const uint32_t kk = (uint32_t)(len - 1) / (uint32_t)(GREEDY ? n + 1 : n);
             K = kk < (uint32_t)a.H ? (int)kk : a.H;
         }
-        Best b;
-        if (a.partial == nullptr) {
+        if (KU > 0) {
+            b = walk_uniform<HMAX, GREEDY, F16>((uint32_t)n, KU, tab, [&](int) { return rsrc; });
+        } else if (a.partial == nullptr) {
             b = walk<HMAX, GREEDY, F16, false>(rsrc, (uint32_t)n, K, tab, a.kmask, 0, nullptr, 0);
         } else {
             float *prow = a.partial + off + n;
@@ -122,20 +197,52 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
     if (a.cand) stage_flush_block<kBlock / 64>(st, a.cand, a.cap, a.count);
 }
 
+// Outputs of fundamental r of plane row i (dense arrays and/or staged
+// candidate records; the bin of a record is i n_r + r).
+__device__ __forceinline__ void plane_out(const Sum2dArgs &a, int i, int64_t r, bool in, const Best &b, Stage &st) {
+    const int64_t o = (int64_t)i * a.n_r + r;
+    if (in) {
+        if (a.snr) a.snr[o] = b.snr;
+        if (a.harm) a.harm[o] = (uint8_t)b.harm;
+        if (a.drift) a.drift[o] = (uint8_t)b.drift;
+    }
+    if (a.cand) {
+        hs_candidate rec;
+        rec.spectrum = 0u;
+        rec.bin = (uint32_t)o;
+        rec.snr = b.snr;
+        rec.harm = (uint16_t)b.harm;
+        rec.drift = (uint16_t)b.drift;
+        stage_push<kPlainStage>(st, a.cand, a.cap, a.count, in && b.harm > 0 && b.snr > a.thr, rec);
+    }
+}
+
 // One column tile of row i: lane owns fundamental r.
 template <int HMAX, bool GREEDY, bool F16>
-__device__ __forceinline__ void walk_2d_tile(const Sum2dArgs &a, int i, int z, int kz, int64_t r, int valid,
-                                             const float2 *tab, Stage &st) {
+__device__ __forceinline__ void walk_2d_tile(const Sum2dArgs &a, int i, int z, int kz, int64_t rt, int valid,
+                                             const ctab_t *tab, int32_t thr, Stage &st) {
     using L = Loader<F16>;
     constexpr uint32_t eb = L::kBytes;
+    const int64_t r = rt + threadIdx.x;
     const bool in = r < a.n_r;
-    int K = 0;
     const int64_t n_end = a.n_end < a.n_r ? a.n_end : a.n_r;
+    const uint32_t row_bytes = (uint32_t)(a.n_r * eb);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int KU = valid ? uniform_k(thr, rt + w * 64, rt + w * 64 + 63, a.first_bin, n_end, a.kmask) : 0;
+    if (KU > 0) {
+        // harmonic k reads row k z: its descriptor is wave-uniform (scalar)
+        const Best b = walk_uniform<HMAX, GREEDY, F16>((uint32_t)r, KU, tab, [&](int k) {
+            const int64_t row = (int64_t)k * z - a.z_min;
+            return make_rsrc((const char *)a.plane + row * a.stride * eb, row_bytes);
+        });
+        plane_out(a, i, r, true, b, st);   // KU > 0: every lane of the wave is inside the row
+        return;
+    }
+    int K = 0;
     if (in && valid && r >= a.first_bin && r < n_end) {
         const uint32_t kk = (uint32_t)(a.n_r - 1) / (uint32_t)(GREEDY ? r + 1 : r);   // n_r < 2^30
         K = kk < (uint32_t)kz ? (int)kk : kz;
     }
-    const uint32_t row_bytes = (uint32_t)(a.n_r * eb);
     float S = 0.0f, best = 0.0f;
     int kb = 0, db = 0;
     uint32_t d = 0, m = (uint32_t)r;
@@ -154,7 +261,7 @@ __device__ __forceinline__ void walk_2d_tile(const Sum2dArgs &a, int i, int z, i
             v = L::one(rs, m);
         }
         S = S + v;
-        const float2 t = tab[k - 1];
+        const float2 t = tab_at(tab, k);
         const float snr = __builtin_fmaf(S, t.x, t.y);
         if ((a.kmask >> (k - 1)) & 1ull) {
             if (kb == 0 || snr > best) {
@@ -165,22 +272,7 @@ __device__ __forceinline__ void walk_2d_tile(const Sum2dArgs &a, int i, int z, i
         }
         m += (uint32_t)r;
     }
-    const Best b{kb ? best : 0.0f, kb, db};
-    const int64_t o = (int64_t)i * a.n_r + r;
-    if (in) {
-        if (a.snr) a.snr[o] = b.snr;
-        if (a.harm) a.harm[o] = (uint8_t)b.harm;
-        if (a.drift) a.drift[o] = (uint8_t)b.drift;
-    }
-    if (a.cand) {
-        hs_candidate rec;
-        rec.spectrum = 0u;
-        rec.bin = (uint32_t)o;
-        rec.snr = b.snr;
-        rec.harm = (uint16_t)b.harm;
-        rec.drift = (uint16_t)b.drift;
-        stage_push<kPlainStage>(st, a.cand, a.cap, a.count, in && b.harm > 0 && b.snr > a.thr, rec);
-    }
+    plane_out(a, i, r, in, Best{kb ? best : 0.0f, kb, db}, st);
 }
 
 // f-fdot plane: blockIdx.y = row i - row0 (z = z_min + i); column tiles of
@@ -193,13 +285,15 @@ __global__ __launch_bounds__(kBlock) void k_sum_2d(Sum2dArgs a) {
     const int z = a.z_min + i;
     const NormRec *nr = a.norm;
     const int valid = nr->valid;
-    const float2 *tab = nr->t;
+    const ctab_t *tab = const_table(nr->t);
     int kz = a.H;
     if (z > 0) kz = a.z_max / z;
     if (z < 0) kz = a.z_min / z;
     if (kz > a.H) kz = a.H;
-    for (int64_t t = blockIdx.x; t * kBlock < a.n_r; t += gridDim.x)
-        walk_2d_tile<HMAX, GREEDY, F16>(a, i, z, kz, t * kBlock + threadIdx.x, valid, tab, st);
+    const int32_t thr = k_threshold<GREEDY>(a.n_r, kz);
+    const int64_t t_lim = (a.snr || a.harm || a.drift) ? a.n_r : (a.n_end < a.n_r ? a.n_end : a.n_r);
+    for (int64_t t = blockIdx.x; t * kBlock < t_lim; t += gridDim.x)
+        walk_2d_tile<HMAX, GREEDY, F16>(a, i, z, kz, t * kBlock, valid, tab, thr, st);
     if (a.cand) stage_flush_block<kBlock / 64>(st, a.cand, a.cap, a.count);
 }
 

@@ -292,12 +292,12 @@ __device__ __forceinline__ void walk_uniform(int KU, __amdgpu_buffer_rsrc_t rsrc
 // p0 + f kBlock + threadIdx.x), restricted to [p0, p_end).  The wave takes
 // the uniform walk when its first and last fundamental (K is non-increasing
 // in n) have the same harmonic count, it holds no bin outside [first_bin,
-// n_end) and the eligibility mask covers harmonics 1..K; else the walk with
-// a bound per lane.  The tests use wave-uniform values only (scalar code).
+// n_end) and the eligibility mask covers harmonics 1..K (uniform_k, from
+// the spectrum's thresholds); else the walk with a bound per lane.
 template <int HMAX, bool GREEDY, bool F16, int F>
 __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInfo &si, int64_t p0, int64_t p_end,
                                           __amdgpu_buffer_rsrc_t rsrc, const float2 *tab, int valid,
-                                          Stage &st) {
+                                          int32_t thr, Stage &st) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t len = si.len;
     int64_t n_end = a.n_end < len ? a.n_end : len;
@@ -305,13 +305,8 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
     uint32_t n[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) n[f] = (uint32_t)(p0 + f * kBlock + threadIdx.x);
-    int KU = 0;
     const int64_t wf = p0 + (int64_t)wave * 64, wl = wf + (F - 1) * kBlock + 63;
-    if (valid && wf >= a.first_bin && wl < n_end) {
-        KU = keff<GREEDY>(wf, len, a.first_bin, n_end, a.H);
-        const uint64_t need = KU >= 64 ? ~0ull : (1ull << KU) - 1ull;
-        if (KU != keff<GREEDY>(wl, len, a.first_bin, n_end, a.H) || (a.kmask & need) != need) KU = 0;
-    }
+    const int KU = valid ? uniform_k(thr, wf, wl, a.first_bin, n_end, a.kmask) : 0;
     float bs[F];
     int kb[F], db[F];
     if (KU > 0)
@@ -386,6 +381,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, F == 
     __shared__ float2 s_tab[HS_MAX_HARMONICS];     // (rs_k, nm_k) of the current spectrum
     Stage st{s_stage[threadIdx.x >> 6], 0};
     int tab_s = -1;                                 // spectrum whose table is in s_tab
+    int thr_s = -1;                                 // spectrum whose harmonic-count thresholds are in thr
+    int32_t thr = -1;
 
     // this queue's slice [g0, g1) of the concatenated chunk list
     const uint32_t total = xa.prefix[xa.n_spectra];
@@ -447,8 +444,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, F == 
         }
         const __amdgpu_buffer_rsrc_t rsrc =
             make_rsrc((const char *)a.x + si.off * eb, (uint32_t)(si.len * eb));
+        if (s != thr_s) {                                      // uniform: thresholds of spectrum s
+            thr = k_threshold<GREEDY>(si.len, a.H);
+            thr_s = s;
+        }
         for (int64_t p0 = lo; p0 < hi; p0 += CH)
-            walk_pass<HMAX, GREEDY, F16, F>(a, s, si, p0, hi, rsrc, s_tab, valid, st);
+            walk_pass<HMAX, GREEDY, F16, F>(a, s, si, p0, hi, rsrc, s_tab, valid, thr, st);
         if (threadIdx.x == 0) s_ticket = next;
         __syncthreads();
         t = __builtin_amdgcn_readfirstlane(s_ticket);
