@@ -356,13 +356,13 @@ hs_status hs_plan_graph_info(hs_plan *plan, int64_t *captures, int64_t *replays)
 /*
  * Launch shape of the persistent kernel (hs_sum_batched and the persistent
  * hs_sum_1d): fundamentals per lane (1, 2 or 4) and resident workgroups of
- * 256 threads per CU (1..4 for 2 and 4 fundamentals per lane, 1..8 for one,
- * bounded by the kernel's occupancy); for a plan with
+ * 256 threads per CU (1..8, bounded by the kernel's occupancy: 6 or 7 on
+ * gfx950); for a plan with
  * HS_KERNEL_AUTO, fundamentals_per_lane 0 makes hs_sum_batched run the plain
  * kernel (workgroups_per_cu ignored; hs_plan_get_launch reports 0, 0).  The
- * results do not depend on the shape.  Default: 4 and the occupancy limit
- * (environment HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan
- * creation).  Setting a new shape drops the plan's cached graphs.
+ * results do not depend on the shape.  Default: 4 and 4 (environment
+ * HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan creation).
+ * Setting a new shape drops the plan's cached graphs.
  */
 hs_status hs_plan_set_launch(hs_plan *plan, int32_t fundamentals_per_lane, int32_t workgroups_per_cu);
 hs_status hs_plan_get_launch(hs_plan *plan, int32_t *fundamentals_per_lane, int32_t *workgroups_per_cu);

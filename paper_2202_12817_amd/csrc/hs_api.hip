@@ -144,9 +144,9 @@ hs_status setup_xcd(hs_plan *p) {
     int per_cu = 0;
     hs_status s = resident_limit(p, p->xcd_f, &per_cu);
     if (s != HS_OK) return s;
-    // default: as many workgroups as are resident (measured fastest for FP32
-    // and FP16 on the 512-spectrum batch); hs_plan_tune_batched searches
-    int want = env_int("HS_XCD_WGS_PER_CU", per_cu);
+    // default: 4 workgroups per CU (or fewer if fewer are resident);
+    // hs_plan_tune_batched searches up to the occupancy limit
+    int want = env_int("HS_XCD_WGS_PER_CU", 4);
     if (want >= 1 && want < per_cu) per_cu = want;
     p->xcd_blocks = per_cu * p->n_cu;
     // LDS bytes of a tile's window in the ray-tiled plane kernel (HS_RAY_LDS
@@ -492,12 +492,12 @@ hs_status dispatch(hs_plan *p, std::vector<uint64_t> &&key, hipStream_t st, Body
 }
 
 // Largest workgroups per CU of the persistent kernel with F fundamentals per
-// lane (compiled for at most 4 waves per SIMD, i.e. 4 workgroups of 256, for
-// F = 2 and 4, and at most 8 for F = 1).
+// lane: what its registers and LDS allow (compiled for at most 8 waves per
+// SIMD, i.e. 8 workgroups of 256).
 hs_status resident_limit(hs_plan *p, int F, int *per_cu) {
     hipError_t e = hs::xcd_resident_blocks(p->hmax, p->desc.mode == HS_GREEDY, p->desc.dtype == HS_F16, F, per_cu);
     if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    const int cap = F == 1 ? 8 : 4;
+    const int cap = 8;
     if (*per_cu > cap) *per_cu = cap;
     if (*per_cu < 1) *per_cu = 1;
     return HS_OK;

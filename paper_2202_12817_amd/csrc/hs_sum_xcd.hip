@@ -365,13 +365,11 @@ __global__ __launch_bounds__(1024) void k_chunk_prefix(const int64_t *offsets, i
     if (threadIdx.x == 0) prefix[n_spectra] = carry;
 }
 
-// Occupancy target: at most 4 waves per SIMD (4 resident workgroups per CU)
-// for F = 2 and 4, which lets the compiler use up to 128 VGPRs, so the
-// unrolled harmonic loop never spills (with the default target it capped
-// VGPRs at 64 and spilled to scratch); F = 1 needs about half the registers
-// and may run 8 workgroups per CU.
+// Occupancy: up to 8 waves per SIMD (8 workgroups of 256 per CU).  The
+// walks need 35-80 VGPRs at every H bucket and F with no scratch, so 6-7
+// workgroups fit per CU; the launch-shape tuner picks how many run.
 template <int HMAX, bool GREEDY, bool F16, int F>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, F == 1 ? 8 : 4))) void k_sum_xcd(XcdArgs xa) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) void k_sum_xcd(XcdArgs xa) {
     constexpr uint32_t eb = Loader<F16>::kBytes;
     constexpr int CH = kBlock * F;                 // fundamentals per pass (class-0 chunk)
     const SumArgs &a = xa.s;
