@@ -360,8 +360,9 @@ hs_status hs_plan_graph_info(hs_plan *plan, int64_t *captures, int64_t *replays)
  * gfx950); for a plan with
  * HS_KERNEL_AUTO, fundamentals_per_lane 0 makes hs_sum_batched run the plain
  * kernel (workgroups_per_cu ignored; hs_plan_get_launch reports 0, 0).  The
- * results do not depend on the shape.  Default: 4 and 4 (environment
- * HS_XCD_F and HS_XCD_WGS_PER_CU override the defaults at plan creation).
+ * results do not depend on the shape.  Default: 2 and 4 for FP32, 4 and 5
+ * for FP16 (environment HS_XCD_F and HS_XCD_WGS_PER_CU override the
+ * defaults at plan creation).
  * Setting a new shape drops the plan's cached graphs.
  */
 hs_status hs_plan_set_launch(hs_plan *plan, int32_t fundamentals_per_lane, int32_t workgroups_per_cu);

@@ -139,14 +139,17 @@ hs_status setup_xcd(hs_plan *p) {
     }
     if (nx > hs::kMaxXcd) nx = hs::kMaxXcd;
     p->n_xcd = nx;
-    int F = env_int("HS_XCD_F", 4);
-    p->xcd_f = (F == 1 || F == 2 || F == 4) ? F : 4;
+    // default shape: what the tuner picks on the 512-spectrum batch (FP32:
+    // 2 fundamentals per lane, 4 workgroups per CU; FP16: 4 and 5), capped
+    // by the occupancy; hs_plan_tune_batched searches up to that limit
+    const bool f16 = p->desc.dtype == HS_F16;
+    const int F0 = f16 ? 4 : 2;
+    int F = env_int("HS_XCD_F", F0);
+    p->xcd_f = (F == 1 || F == 2 || F == 4) ? F : F0;
     int per_cu = 0;
     hs_status s = resident_limit(p, p->xcd_f, &per_cu);
     if (s != HS_OK) return s;
-    // default: 4 workgroups per CU (or fewer if fewer are resident);
-    // hs_plan_tune_batched searches up to the occupancy limit
-    int want = env_int("HS_XCD_WGS_PER_CU", 4);
+    int want = env_int("HS_XCD_WGS_PER_CU", f16 ? 5 : 4);
     if (want >= 1 && want < per_cu) per_cu = want;
     p->xcd_blocks = per_cu * p->n_cu;
     // LDS bytes of a tile's window in the ray-tiled plane kernel (HS_RAY_LDS
