@@ -179,10 +179,10 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
                 for (uint64_t rm = a.report_mask, slot = 0; rm; rm &= rm - 1, ++slot) prow[slot * len] = 0.0f;
             b = walk<HMAX, GREEDY, F16, true>(rsrc, (uint32_t)n, K, tab, a.kmask, a.report_mask, prow, len);
         }
-        if (in) {
-            if (a.snr) a.snr[off + n] = b.snr;
-            if (a.harm) a.harm[off + n] = (uint8_t)b.harm;
-            if (a.drift) a.drift[off + n] = (uint8_t)b.drift;
+        if (in) {   // outputs are never read again: non-temporal stores
+            if (a.snr) __builtin_nontemporal_store(b.snr, a.snr + off + n);
+            if (a.harm) __builtin_nontemporal_store((uint8_t)b.harm, a.harm + off + n);
+            if (a.drift) __builtin_nontemporal_store((uint8_t)b.drift, a.drift + off + n);
         }
         if (a.cand) {
             hs_candidate rec;
@@ -201,10 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_sum_1d(SumArgs a) {
 // candidate records; the bin of a record is i n_r + r).
 __device__ __forceinline__ void plane_out(const Sum2dArgs &a, int i, int64_t r, bool in, const Best &b, Stage &st) {
     const int64_t o = (int64_t)i * a.n_r + r;
-    if (in) {
-        if (a.snr) a.snr[o] = b.snr;
-        if (a.harm) a.harm[o] = (uint8_t)b.harm;
-        if (a.drift) a.drift[o] = (uint8_t)b.drift;
+    if (in) {   // outputs are never read again: non-temporal, so they do not crowd the rows out of L2
+        if (a.snr) __builtin_nontemporal_store(b.snr, a.snr + o);
+        if (a.harm) __builtin_nontemporal_store((uint8_t)b.harm, a.harm + o);
+        if (a.drift) __builtin_nontemporal_store((uint8_t)b.drift, a.drift + o);
     }
     if (a.cand) {
         hs_candidate rec;

@@ -316,11 +316,11 @@ __device__ __forceinline__ void walk_pass(const SumArgs &a, int s, const SpecInf
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const bool in = (int64_t)n[f] < p_end;
-        if (in) {
+        if (in) {   // outputs are never read again: non-temporal stores
             const int64_t o = si.off + n[f];
-            if (a.snr) a.snr[o] = bs[f];
-            if (a.harm) a.harm[o] = (uint8_t)kb[f];
-            if (a.drift) a.drift[o] = (uint8_t)db[f];
+            if (a.snr) __builtin_nontemporal_store(bs[f], a.snr + o);
+            if (a.harm) __builtin_nontemporal_store((uint8_t)kb[f], a.harm + o);
+            if (a.drift) __builtin_nontemporal_store((uint8_t)db[f], a.drift + o);
         }
         if (a.cand) {
             hs_candidate r;
