@@ -56,6 +56,36 @@ __device__ __forceinline__ void acc1(dd &s1, dd &s2, float v) {
     s2 = dd_add_d(s2, dv * dv);      // the square of a float is exact in double
 }
 
+// Running sum x of 16-bit storage: every finite binary16 value is an integer
+// multiple of 2^-24 of magnitude at most 2^40 - 2^29 in those units, so any
+// sum of fewer than 8192 of them is an integer below 2^53 units and a plain
+// double holds it exactly.  The partial sum is folded into the double-double
+// sum every kFlush16 elements (one exact addition instead of a double-double
+// step per element); sum x^2 keeps the double-double step.
+constexpr int kFlush16 = 4096;
+
+struct Part16 {
+    double a1 = 0.0;   // exact partial sum x
+    int cnt = 0;       // elements in a1
+};
+
+__device__ __forceinline__ void acc16(Part16 &p, dd &s2, float v) {
+    const double dv = (double)v;
+    p.a1 += dv;                      // exact (see above)
+    s2 = dd_add_d(s2, dv * dv);      // the square of a float is exact in double
+    ++p.cnt;
+}
+
+// Fold the partial sum once it holds kFlush16 elements or more (at most
+// kFlush16 + 7: still far below the 8192 that keep it exact).
+__device__ __forceinline__ void flush16(Part16 &p, dd &s1, int at_least) {
+    if (p.cnt >= at_least) {
+        s1 = dd_add_d(s1, p.a1);
+        p.a1 = 0.0;
+        p.cnt = 0;
+    }
+}
+
 // Accumulate elements [lo, hi) of the array x (element units; x 16-byte
 // aligned).  The full 16-byte vectors inside the range are read with vector
 // loads, the ragged head and tail element by element, so nothing outside
@@ -63,29 +93,38 @@ __device__ __forceinline__ void acc1(dd &s1, dd &s2, float v) {
 template <bool F16>
 __device__ __forceinline__ void accumulate(const char *x, int64_t lo, int64_t hi, dd &s1, dd &s2) {
     constexpr int64_t V = F16 ? 8 : 4;
+    Part16 p;
+    auto acc = [&](float v) {
+        if constexpr (F16)
+            acc16(p, s2, v);
+        else
+            acc1(s1, s2, v);
+    };
     int64_t q0 = (lo + V - 1) / V, q1 = hi / V;
     if (q0 >= q1) {                          // no full vector: all element-wise
-        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) acc1(s1, s2, elem_at<F16>(x, e));
-        return;
-    }
-    for (int64_t e = lo + threadIdx.x; e < q0 * V; e += blockDim.x) acc1(s1, s2, elem_at<F16>(x, e));
-    for (int64_t e = q1 * V + threadIdx.x; e < hi; e += blockDim.x) acc1(s1, s2, elem_at<F16>(x, e));
-    const uint4 *vp = (const uint4 *)x;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-        uint4 raw = vp[q];
-        uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) acc(elem_at<F16>(x, e));
+    } else {
+        for (int64_t e = lo + threadIdx.x; e < q0 * V; e += blockDim.x) acc(elem_at<F16>(x, e));
+        for (int64_t e = q1 * V + threadIdx.x; e < hi; e += blockDim.x) acc(elem_at<F16>(x, e));
+        const uint4 *vp = (const uint4 *)x;
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+            uint4 raw = vp[q];
+            uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-        for (int j = 0; j < (int)V; ++j) {
-            float v;
-            if constexpr (F16) {
-                unsigned short b = (unsigned short)(w[j >> 1] >> ((j & 1) * 16));
-                v = (float)__builtin_bit_cast(_Float16, b);
-            } else {
-                v = __builtin_bit_cast(float, w[j]);
+            for (int j = 0; j < (int)V; ++j) {
+                float v;
+                if constexpr (F16) {
+                    unsigned short b = (unsigned short)(w[j >> 1] >> ((j & 1) * 16));
+                    v = (float)__builtin_bit_cast(_Float16, b);
+                } else {
+                    v = __builtin_bit_cast(float, w[j]);
+                }
+                acc(v);
             }
-            acc1(s1, s2, v);
+            if constexpr (F16) flush16(p, s1, kFlush16);
         }
     }
+    if constexpr (F16) flush16(p, s1, 1);
 }
 
 template <bool F16>
