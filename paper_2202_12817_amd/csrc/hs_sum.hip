@@ -9,9 +9,11 @@
 //   best: strictly larger SNR among the k selected by the mask.
 // Consecutive lanes own consecutive fundamentals, so harmonic k of a wave
 // reads a window of 64 k bins (strided by k); the greedy pair is one 8-byte
-// buffer load.  The normalisation table is wave-uniform and lives in SGPRs.
-// K = min(H, (N-1) / (n + greedy)) keeps every read inside the spectrum; the
-// buffer descriptors additionally bound every read by the spectrum's size.
+// buffer load.  The normalisation table is wave-uniform and read with
+// scalar loads.  K = min(H, (N-1) / (n + greedy)) keeps every read inside
+// the spectrum; the buffer descriptors additionally bound every read by the
+// spectrum's size.  A wave whose 64 fundamentals share K (almost all of
+// them) takes walk_uniform, without per-lane bounds; the others take walk.
 #include "hs_internal.h"
 
 namespace hs {
