@@ -21,10 +21,12 @@
 // workgroup: every wave reaches the exit.
 //
 // Per lane: F fundamentals (p0 + threadIdx.x + f kBlock) walked harmonic by
-// harmonic with independent loads in flight.  The harmonic loop bound is
-// wave-uniform (the largest K of the wave); a lane whose own K is smaller
-// issues its loads at an out-of-range buffer offset, which returns zero
-// without touching memory, and commits nothing.
+// harmonic with independent loads in flight.  When every fundamental of the
+// wave sums the same number of harmonics K, all eligible (almost every
+// wave), the walk has no per-lane bound (walk_uniform).  Otherwise the loop
+// bound is the wave's largest K and a lane whose own K is smaller issues its
+// loads at an out-of-range buffer offset, which returns zero without
+// touching memory, and commits nothing (walk_lanes).
 #include "hs_internal.h"
 
 namespace hs {
