@@ -109,13 +109,27 @@ __device__ __forceinline__ Best walk_uniform(uint32_t n, int KU, const ctab_t *t
             md = nx;
         }
     } else {
-        // the reads do not depend on the data: groups of four harmonics are
-        // loaded together (one basic block, four loads in flight), then the
-        // one to three left over, again together
+        // the reads do not depend on the data: groups of harmonics are loaded
+        // together (one basic block; eight loads in flight in the buckets of
+        // 32 and 64 harmonics, where the lowest fundamentals' 32-step walks
+        // set a single spectrum's time, four in the smaller buckets, where
+        // eight measured slower on the plane), then the one to three left
+        // over, again together
         int k = 1;
-        while (k + 3 <= KU) {                               // wave-uniform
-            simple_block<4, F16>(k, md, n, row, update);
-            k += 4;
+        if constexpr (HMAX >= 32) {
+            while (k + 7 <= KU) {                           // wave-uniform
+                simple_block<8, F16>(k, md, n, row, update);
+                k += 8;
+            }
+            if (k + 3 <= KU) {
+                simple_block<4, F16>(k, md, n, row, update);
+                k += 4;
+            }
+        } else {
+            while (k + 3 <= KU) {                           // wave-uniform
+                simple_block<4, F16>(k, md, n, row, update);
+                k += 4;
+            }
         }
         const int r = KU - k + 1;
         if (r == 3)
