@@ -269,6 +269,20 @@ def plane_2d_leg(hs, torch, dev, steps, warmup, error=True, kernel="auto"):
     out = {"workload": "f-fdot plane %d x %d (z = %d..%d), H=%d, dense snr/harm/drift" % (n_r, n_z, z_min, z_max, h2),
            "kernel": kernel}
     mu_sigma = torch.zeros(2, dtype=torch.float64, device=dev)
+    # the rate of a plain elementwise read-write kernel on this machine, measured
+    # here: the ceiling for the bytes the plane kernels move (they read the
+    # plane and write three outputs)
+    tmp = outs["f32"][0]
+    for _ in range(3):
+        torch.neg(p32, out=tmp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.neg(p32, out=tmp)
+    e1.record()
+    torch.cuda.synchronize()
+    rw_gbs = 2 * p32.numel() * 4 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    out["elementwise_rw_gbs"] = rw_gbs
     for mname, mode in (("standard", hs.HS_STANDARD), ("greedy", hs.HS_GREEDY)):
         for dname, dt, pin, eb in (("f32", hs.HS_F32, p32, 4), ("f16", hs.HS_F16, p16, 2)):
             snr, harm, drift = outs[dname]
@@ -291,11 +305,25 @@ def plane_2d_leg(hs, torch, dev, steps, warmup, error=True, kernel="auto"):
             work = keff_sum_2d(n_r, z_min, z_max, h2, mode == hs.HS_GREEDY)
             comp = n_z * n_r * (eb + 6)
             sum_ms = sm / max(1, c)
+            kern = "k_sum_2d<%d, %s, %s>" % (h2, "true" if mode == hs.HS_GREEDY else "false",
+                                                "true" if dname == "f16" else "false")
+            rec = read_counters(kern) if kernel != "persistent" else None
+            moved = rec["fetch_bytes"] + rec["write_bytes"] if rec and "fetch_bytes" in rec and \
+                "write_bytes" in rec else None
+            roof = {"bound": "hbm", "kernel": kern, "achieved": comp / (sum_ms * 1e-3) / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "traffic": moved}
+            if moved:
+                mv = moved / (sum_ms * 1e-3) / 1e9
+                roof["moved"] = {"achieved": mv, "peak": rw_gbs, "unit": "GB/s", "frac": mv / rw_gbs,
+                                 "what": "bytes fetched and written (committed FETCH_SIZE + WRITE_SIZE) vs an "
+                                         "elementwise read-write kernel's rate measured in this run"}
             out["%s_%s" % (dname, mname)] = {
                 "value": work / el, "unit": "bin·harmonics/s", "ms_per_step": 1e3 * el,
                 "stage_ms": {"normalisation": nm / max(1, c), "harmonic_sum": sum_ms},
                 "sum_kernel_gbs_compulsory": comp / (sum_ms * 1e-3) / 1e9,
-                "sum_kernel_frac_compulsory": comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                "sum_kernel_frac_compulsory": comp / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "roofline": roof}
         if error:
             torch.cuda.synchronize()
             ms = mu_sigma.cpu().numpy()
